@@ -1,0 +1,246 @@
+"""Pins of the oracle's normalise + PNN hole fill (Sec. II.C) and of the bone-depth map
+and slab projection (Sec. II.D, Tables I-II; VPI baseline of Sec. III.B): hand-worked
+cases, closed forms, a library convolution and the cfg-1 ground-truth band."""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+
+
+def G(dims, o=(0.0, 0.0, 0.0), s=0.5):
+    return synth.Grid(tuple(dims), tuple(o), s)
+
+
+def _fin(dims, sum_, cnt, fill_min=1):
+    return oracle.finalize(G(dims), np.asarray(sum_, np.uint32).ravel(), np.asarray(cnt, np.uint16).ravel(), fill_min)
+
+
+def test_normalise_round_half_up_and_cap():
+    # (sum, cnt) -> V: 5/2 = 2.5 -> 3, 7/3 = 2.33 -> 2, 8/3 = 2.67 -> 3, 510/2 = 255, 0/1 = 0
+    s = np.array([5, 7, 8, 510, 0, 1000, 0], np.uint32)
+    c = np.array([2, 3, 3, 2, 1, 2, 0], np.uint16)
+    V, st, bad = _fin((7, 1, 1), s, c)
+    assert V.ravel()[:6].tolist() == [3, 2, 3, 255, 0, 255]
+    assert st.ravel()[:6].tolist() == [1] * 6
+    assert bad == 1          # 1000 > 255 * 2
+    # the cnt = 0 voxel is filled from its one in-grid neighbour (x = 5, V = 255)
+    assert st.ravel()[6] == 2 and V.ravel()[6] == 255
+
+
+def test_hole_in_constant_field_keeps_constant():
+    dims = (5, 5, 5)
+    cnt = np.ones((5, 5, 5), np.uint16) * 2
+    sm = np.full((5, 5, 5), 2 * 77, np.uint32)
+    cnt[2, 2, 2] = 0
+    sm[2, 2, 2] = 0
+    V, st, _ = _fin(dims, sm, cnt)
+    assert V[2, 2, 2] == 77 and st[2, 2, 2] == 2
+    assert np.all(V == 77) and (st == 1).sum() == 124
+
+
+def test_two_neighbours_round_half_up():
+    dims = (3, 1, 1)
+    for a, b in [(10, 11), (0, 255), (100, 100), (1, 2)]:
+        V, st, _ = _fin(dims, [a, 0, b], [1, 0, 1])
+        assert V.ravel()[1] == math.floor((a + b) / 2 + 0.5)
+        assert st.ravel().tolist() == [1, 2, 1]
+
+
+def test_fully_measured_is_identity_and_isolated_hole_stays_empty():
+    g = np.random.default_rng(1)
+    c = g.integers(1, 9, (4, 5, 6)).astype(np.uint16)
+    v = g.integers(0, 256, (4, 5, 6))
+    V, st, _ = _fin((6, 5, 4), v * c, c)
+    assert np.array_equal(V, v) and np.all(st == 1)
+    c = np.zeros((5, 5, 5), np.uint16)
+    c[0, 0, 0] = 1
+    V, st, _ = _fin((5, 5, 5), c.astype(np.uint32) * 9, c)
+    assert st[4, 4, 4] == 0 and V[4, 4, 4] == 0 and st[1, 1, 1] == 2 and V[1, 1, 1] == 9
+
+
+def test_fill_min_threshold():
+    c = np.zeros((3, 3, 3), np.uint16)
+    c[0, 0, 0] = 1
+    c[2, 2, 2] = 1
+    s = c.astype(np.uint32) * 40
+    V, st, _ = _fin((3, 3, 3), s, c, fill_min=2)
+    assert st[1, 1, 1] == 2 and V[1, 1, 1] == 40     # sees both corners
+    assert st[0, 0, 1] == 0 and V[0, 0, 1] == 0      # sees one only
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_hole_fill_matches_library_convolution(seed):
+    g = np.random.default_rng(seed)
+    shape = (8, 9, 10)
+    c = (g.random(shape) < 0.35) * g.integers(1, 5, shape)
+    v = g.integers(0, 256, shape)
+    s = v * c
+    V, st, _ = _fin(shape[::-1], s, c)
+    meas = c > 0
+    Vn = np.where(meas, (2 * s + c) // np.maximum(2 * c, 1), 0)
+    k = np.ones((3, 3, 3), np.int64)
+    k[1, 1, 1] = 0
+    nsum = ndimage.convolve((Vn * meas).astype(np.int64), k, mode="constant", cval=0)
+    ncnt = ndimage.convolve(meas.astype(np.int64), k, mode="constant", cval=0)
+    fill = (~meas) & (ncnt >= 1)
+    want = np.where(meas, Vn, np.where(fill, (2 * nsum + ncnt) // np.maximum(2 * ncnt, 1), 0))
+    want_st = np.where(meas, 1, np.where(fill, 2, 0))
+    assert np.array_equal(V, want) and np.array_equal(st, want_st)
+
+
+# --- segmentation + projection ----------------------------------------------------------
+
+
+def _col_volume(cols, ny):
+    """Volume whose (x=i, z=0) column is cols[i] (all voxels MEASURED)."""
+    nx = len(cols)
+    V = np.zeros((1, ny, nx), np.uint8)
+    for i, c in enumerate(cols):
+        V[0, :, i] = c
+    return V, np.ones_like(V)
+
+
+def test_alg2_bright_over_dark_shadow():
+    ny, k = 40, 6
+    col = np.full(ny, 60, np.uint8)
+    col[17] = 220
+    col[18:18 + k] = 0
+    V, st = _col_volume([col], ny)
+    p = oracle.seg_params(mode=oracle.ALG2, k=k, tau_I=128, tau_G=40, r=0, fallback_y=3, half=(2,))
+    d, mean, mx = oracle.segment(G((1, ny, 1)), V, st, p)
+    assert d[0, 0] == 17
+
+
+def test_alg2_constant_column_falls_back():
+    V, st = _col_volume([np.full(30, 200, np.uint8)], 30)
+    p = oracle.seg_params(mode=oracle.ALG2, r=0, fallback_y=11, half=(2,))
+    d, _, _ = oracle.segment(G((1, 30, 1)), V, st, p)
+    assert d[0, 0] == 11
+
+
+def test_alg2_ties_resolve_to_deepest():
+    ny, k = 60, 6
+    col = np.zeros(ny, np.uint8)
+    col[10] = 200
+    col[30] = 200
+    col[45] = 150
+    V, st = _col_volume([col], ny)
+    p = oracle.seg_params(mode=oracle.ALG2, k=k, r=0, half=(2,))
+    d, _, _ = oracle.segment(G((1, ny, 1)), V, st, p)
+    assert d[0, 0] == 30          # s(10) = s(30) = 1200 > s(45) = 900: deepest of the tie
+
+
+def test_alg2_y_range_excludes_top_and_tail():
+    ny, k = 20, 6
+    col = np.zeros(ny, np.uint8)
+    col[2] = 250
+    col[16] = 250                  # > ny-1-k = 13: never scanned
+    V, st = _col_volume([col], ny)
+    p = oracle.seg_params(mode=oracle.ALG2, k=k, r=0, y_lo=3, fallback_y=5, half=(1,))
+    d, _, _ = oracle.segment(G((1, ny, 1)), V, st, p)
+    assert d[0, 0] == 5
+
+
+def test_median_window_matches_numpy_lower_median():
+    g = np.random.default_rng(4)
+    nx, nz, ny, k = 9, 7, 50, 6
+    raw = g.integers(-1, 40, (nz, nx))       # -1 = no contour in that column
+    V = np.zeros((nz, ny, nx), np.uint8)
+    for z in range(nz):
+        for x in range(nx):
+            if raw[z, x] >= 0:
+                V[z, raw[z, x], x] = 200
+    st = np.ones_like(V)
+    p = oracle.seg_params(mode=oracle.ALG2, k=k, r=2, fallback_y=44, half=(1,))
+    d, _, _ = oracle.segment(G((nx, ny, nz)), V, st, p)
+    for z in range(nz):
+        for x in range(nx):
+            w = raw[max(0, z - 2):z + 3, max(0, x - 2):x + 3].ravel()
+            w = np.sort(w[w >= 0])
+            want = 44 if w.size == 0 else w[(w.size - 1) // 2]
+            assert d[z, x] == want
+
+
+def test_slab_on_ramp():
+    # V(y) = y, all measured; FIXED depth d = 20: mean = d, max = d + h
+    ny = 40
+    V, st = _col_volume([np.arange(ny, dtype=np.uint8)], ny)
+    p = oracle.seg_params(mode=oracle.FIXED, D_mm=10.2, yref_mm=0.0, half=(2, 5, 10))
+    d, mean, mx = oracle.segment(G((1, ny, 1)), V, st, p)
+    assert d[0, 0] == 20
+    assert mean[:, 0, 0].tolist() == [20.0, 20.0, 20.0]
+    assert mx[:, 0, 0].tolist() == [22.0, 25.0, 30.0]
+    # clipped at the volume edge: d = 38, h = 5 -> y in [33, 39]
+    p = oracle.seg_params(mode=oracle.FIXED, D_mm=19.0, half=(5,))
+    d, mean, mx = oracle.segment(G((1, ny, 1)), V, st, p)
+    assert d[0, 0] == 38 and mean[0, 0, 0] == np.float32(36.0) and mx[0, 0, 0] == 39.0
+
+
+def test_slab_excludes_empty_and_fixed_is_textbook_average():
+    g = np.random.default_rng(9)
+    nx, ny, nz = 6, 30, 5
+    V = g.integers(0, 256, (nz, ny, nx)).astype(np.uint8)
+    st = (g.random((nz, ny, nx)) < 0.7).astype(np.uint8) * g.integers(1, 3, (nz, ny, nx)).astype(np.uint8)
+    p = oracle.seg_params(mode=oracle.FIXED, D_mm=7.3, yref_mm=0.5, half=(3,))
+    d, mean, mx = oracle.segment(G((nx, ny, nz), o=(0.0, -1.0, 0.0)), V, st, p)
+    dd = math.floor((0.5 + 7.3 + 1.0) / 0.5)
+    assert np.all(d == dd)
+    sl = V[:, dd - 3:dd + 4, :].astype(np.float64)
+    ok = st[:, dd - 3:dd + 4, :] != 0
+    cnt = ok.sum(1)
+    want = np.where(cnt > 0, (sl * ok).sum(1) / np.maximum(cnt, 1), 0.0).astype(np.float32)
+    assert np.array_equal(mean[0], want)
+    assert np.array_equal(mx[0], np.where(cnt > 0, (sl * ok).max(1), 0).astype(np.float32))
+
+
+def test_alg1_hand_computed_depths():
+    # grid z centres at (z + 1/2) 0.5; z1 = 1.0, L = 20, K = 0.5, D = 4, yref = 2, o_y = 0
+    nx, ny, nz = 2, 60, 40
+    V = np.zeros((nz, ny, nx), np.uint8)
+    p = oracle.seg_params(mode=oracle.ALG1, K=0.5, D_mm=4.0, L_mm=20.0, z1_mm=1.0, yref_mm=2.0, half=(1,))
+    d, _, _ = oracle.segment(G((nx, ny, nz)), V, V, p)
+    for z, want_mm in [(0, 0.5 * abs(abs(0.25 - 1.0) - 10) + 4), (21, 0.5 * abs(abs(10.75 - 1.0) - 10) + 4),
+                       (39, 0.5 * abs(abs(19.75 - 1.0) - 10) + 4)]:
+        assert d[z, 0] == d[z, 1] == math.floor((2.0 + want_mm) / 0.5)
+    # shallow in the middle of the back, deeper at both ends (Table I)
+    assert d[21, 0] < d[0, 0] and d[21, 0] < d[39, 0]
+
+
+def test_cfg1_band_ground_truth():
+    """The band at image rows 40-50 is bright over darker speckle: ALG2 must put the depth
+    at the band's bottom voxel (from exact FP64 geometry) within +-1 on >= 95% of the
+    columns that hold data."""
+    d = synth.cfg1()
+    grid = d["grid"]
+    acc = oracle.Accum(grid)
+    acc.ingest(d["frames"], d["poses"], d["probe"])
+    V, st, _ = oracle.finalize(grid, acc.sum, acc.cnt)
+    p = oracle.seg_params(mode=oracle.ALG2, r=2, fallback_y=-1, half=(2,))
+    dep, _, _ = oracle.segment(grid, V, st, p)
+    nx, ny, nz = grid.dims
+    sx = d["probe"].pixel_mm[0]
+    good = total = 0
+    for z in range(nz):
+        zc = (z + 0.5) * 0.5
+        n = int(round((zc - 8.0) / 0.5))
+        if n < 2 or n > 61:
+            continue
+        A = d["poses"][n]
+        for x in range(nx):
+            if st[z, :, x].sum() == 0:
+                continue
+            xc = (x + 0.5) * 0.5
+            # image column under this voxel column, then the world y of the band's bottom edge
+            u_mm = np.linalg.solve(A[:2, :2], np.array([xc, 16.0]) - A[:2, 3])[0]
+            if not (1.0 < u_mm < 128 * sx - 1.0):
+                continue
+            y_edge = (A @ np.array([u_mm, 51 * sx, 0.0, 1.0]))[1]
+            want = math.floor((y_edge - 0.15) / 0.5)
+            total += 1
+            good += abs(int(dep[z, x]) - want) <= 1
+    assert total > 2000
+    assert good >= 0.95 * total, (good, total)
