@@ -1,0 +1,272 @@
+/*
+ * usv.h -- C ABI of the MI355X (gfx950) free-hand ultrasound compounding library.
+ *
+ * The library turns tracked 2D B-mode frames into a voxel volume the way the paper's
+ * real-time system does (Li, Shen et al., whole-spine free-hand ultrasound):
+ *   - every pixel is carried into the reconstruction (camera) frame by the chain
+ *     T_Wn^Cam T_T^W of Table I Steps 2, 3, 6 and Table II Step 5;
+ *   - pixel-nearest-neighbour (PNN) compounding, incremental: only newly acquired
+ *     frames are added to a persistent reconstruction (Sec. II.C);
+ *   - PNN hole filling of unobserved voxels (Sec. II.C);
+ *   - only the region touched by new data needs reprocessing (Sec. II.C);
+ *   - bone-depth (cut-depth) estimation by the pose formula of Table I Step 4 or by
+ *     bright / high-gradient contours with median filtering (Table II Steps 2-3),
+ *     and slab projections at that depth (Sec. II.D; fixed-depth VPI of Sec. III.B).
+ * Beside the paper's path: a differentiable trilinear splat with a hand-written
+ * backward to per-frame se(3) poses and intensities, a batched multi-sweep ingest
+ * and a captured (HIP graph) single-frame ingest.
+ *
+ * Conventions
+ *   - Frames: uint8, row v (depth, 0 at the probe face) by column u; pixel (u, v)
+ *     sits at image point ((u+1/2) sx, (v+1/2) sy, 0) mm.
+ *   - Poses: FP64 4x4 row-major T_Wn^Cam per frame; calibration T_T^W per probe.
+ *   - Grid: dims (nx, ny, nz); origin = world position (mm) of the corner of voxel
+ *     (0,0,0); isotropic voxel size.  Voxel (x, y, z) has linear index
+ *     x + nx (y + ny z) and covers [x, x+1) x [y, y+1) x [z, z+1) in voxel units.
+ *   - Accumulators (caller-owned device memory, usv_accumulator_bytes bytes):
+ *     uint32 sum[nvox] followed by uint16 cnt[nvox rounded up to even].
+ *   - Every call is ordered on the stream given to usv_create_volume (a hipStream_t
+ *     passed as void*; NULL = the default stream) and is asynchronous unless noted.
+ *     Device buffers belong to the caller; the library owns only the opaque objects,
+ *     small tables and staging memory, all released by the matching destroy call.
+ *   - Errors: argument errors return USV_E_ARG synchronously and change nothing.
+ *     Device errors and count overflow are sticky: they are latched and reported by
+ *     usv_sync (and by later calls on the same volume).  Objects are thread
+ *     compatible (one thread at a time per object), not thread safe.
+ *   - Numbers: the nearest-voxel path is bit-exact: the pose chain is folded in FP64
+ *     and rounded once to FP32; voxel coordinates are evaluated in FP32 with no
+ *     fused multiply-add in the order stated at usv_ingest_frames.
+ */
+#ifndef USV_H
+#define USV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  USV_OK = 0,
+  USV_E_ARG = -1,             /* invalid argument (nothing was enqueued) */
+  USV_E_OOM = -2,             /* library-internal allocation failed */
+  USV_E_DEVICE = -3,          /* HIP runtime / kernel launch error (sticky) */
+  USV_E_STATE = -4,           /* call not valid in the object's current state */
+  USV_E_COUNT_OVERFLOW = -5,  /* a voxel received more than 65535 pixels (sticky) */
+  USV_E_UNSUPPORTED = -6      /* valid request the library does not implement */
+} usv_status;
+
+typedef struct usv_volume usv_volume;
+typedef struct usv_graph usv_graph;
+typedef struct usv_splat usv_splat;
+
+/* Voxel box [lo, hi) per axis (x, y, z); empty when lo[a] >= hi[a] for some a. */
+typedef struct {
+  int32_t lo[3], hi[3];
+} usv_box;
+
+/* Reconstruction grid.  fill_min: minimum number of measured 26-neighbours for the
+ * PNN hole fill of an empty voxel (>= 1; 0 is read as 1). */
+typedef struct {
+  int32_t dims[3];
+  double origin_mm[3];
+  double voxel_mm;
+  int32_t fill_min;
+} usv_grid_desc;
+
+/* Probe / image geometry (Sec. II.B: the image-to-marker calibration T_T^W is fixed
+ * per probe).  mask_host: optional H*W bytes, nonzero = inside the imaging fan (e.g. a
+ * convex sector); NULL = every pixel is image data.  The mask is copied. */
+typedef struct {
+  int32_t width, height;
+  double pixel_mm[2];
+  double calib[16];
+  const uint8_t *mask_host;
+} usv_probe_desc;
+
+/* Bone-depth estimation + slab projection (Sec. II.D).
+ * mode USV_SEG_ALG2 (Table II Steps 2-3): per column (x, z), over y in
+ *   [y_lo, ny-1-k], s(y) = k V(y) - sum_{j=1..k} V(y+j); y is a contour candidate iff
+ *   V(y) >= tau_I and s(y) >= k tau_G; the raw depth is the candidate of largest s
+ *   (ties: largest y), -1 if none; the depth is the lower median (element
+ *   floor((n-1)/2) of the sorted valid raw depths) over the (2r+1)^2 window in
+ *   (x, z), clipped at the grid edge, or fallback_y when the window holds none.
+ * mode USV_SEG_ALG1 (Table I Step 4): per slice z, z_c = o_z + (z+1/2) s,
+ *   Cut = K | |z_c - z1_mm| - L_mm/2 | + D_mm, depth = clamp(floor((yref_mm + Cut -
+ *   o_y) / s), 0, ny-1) (FP64).
+ * mode USV_SEG_FIXED (VPI): depth = clamp(floor((yref_mm + D_mm - o_y) / s), 0, ny-1).
+ * Projection for each of the n_half half widths h: over y in [max(0, d-h),
+ *   min(ny-1, d+h)] and voxels whose state is not EMPTY: mean = (float)sum /
+ *   (float)count (0 if none), max = (float)max (0 if none). */
+enum { USV_SEG_ALG2 = 0, USV_SEG_ALG1 = 1, USV_SEG_FIXED = 2 };
+typedef struct {
+  int32_t mode;
+  int32_t y_lo, k, tau_I, tau_G, r, fallback_y, n_half;
+  int32_t half[4];
+  double K, D_mm, L_mm, z1_mm, yref_mm;
+} usv_seg_params;
+
+/* Voxel states written by usv_finalize. */
+enum { USV_EMPTY = 0, USV_MEASURED = 1, USV_FILLED = 2 };
+
+/* ---------------------------------------------------------------------------------
+ * Volume lifetime
+ * --------------------------------------------------------------------------------- */
+
+/* Bytes of the accumulator buffer for a grid (0 if the grid is invalid). */
+size_t usv_accumulator_bytes(const usv_grid_desc *grid);
+
+/* Create a volume over caller-owned device memory accum_dev (usv_accumulator_bytes,
+ * 4-byte aligned), zeroing it on `stream`.  dims must be >= 1 with nx*ny*nz < 2^31;
+ * voxel_mm > 0 and finite.  *out receives the handle. */
+usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *stream, usv_volume **out);
+
+/* Register a probe (image geometry + calibration + optional fan mask), returning its
+ * id.  Width/height 1..32767, pixel sizes > 0.  Up to 16 probes per volume. */
+usv_status usv_add_probe(usv_volume *vol, const usv_probe_desc *probe, int32_t *probe_id);
+
+/* Zero the accumulators (start a new sweep). */
+usv_status usv_reset(usv_volume *vol);
+
+/* Wait for the volume's stream and report the sticky status (USV_OK,
+ * USV_E_COUNT_OVERFLOW or USV_E_DEVICE).  Synchronous. */
+usv_status usv_sync(usv_volume *vol);
+
+/* Copy the accumulators to / from caller device memory (checkpoint / resume of the
+ * incremental state; usv_accumulator_bytes bytes). */
+usv_status usv_export_accumulators(usv_volume *vol, void *dst_dev);
+usv_status usv_import_accumulators(usv_volume *vol, const void *src_dev);
+
+usv_status usv_destroy_volume(usv_volume *vol);
+
+/* Text of the last error on this volume ("" if none).  Valid until the next call. */
+const char *usv_last_error(const usv_volume *vol);
+
+/* ---------------------------------------------------------------------------------
+ * Incremental PNN compounding (Sec. II.C)
+ * --------------------------------------------------------------------------------- */
+
+/* Add n frames taken with probe probe_id.  frames_dev: uint8 device memory, frame i
+ * row v column u at frames_dev[i*frame_pitch + v*row_pitch + u].  poses_host: n*16
+ * FP64 (T_Wn^Cam, row major), read before the call returns.
+ * Per frame the library forms T = A C (A = pose, C = calibration, products summed in
+ * index order in FP64) and the FP32 map
+ *   M[r] = (T[r][0] sx / s,  T[r][1] sy / s,
+ *           (((T[r][3] + (sx/2) T[r][0]) + (sy/2) T[r][1]) - o[r]) / s),
+ * then per pixel, in FP32 without contraction,
+ *   c_r = fl(fl(M[r][1] v) + M[r][2]),  q_r = fl(fl(M[r][0] u) + c_r);
+ * the pixel is kept iff inside the mask and 0 <= q_r < n_r for all r, and is added to
+ * voxel (floor q_x, floor q_y, floor q_z): sum += value, cnt += 1.
+ * Frames whose folded map is not finite add nothing; a folded entry of magnitude
+ * >= 2^64 is rejected (USV_E_ARG).  dirty_out (nullable) receives the voxel box that
+ * holds every voxel this call can have changed (empty box if none). */
+usv_status usv_ingest_frames(usv_volume *vol, int32_t probe_id, const uint8_t *frames_dev, int64_t row_pitch,
+                             int64_t frame_pitch, const double *poses_host, int32_t n, usv_box *dirty_out);
+
+/* Normalise + hole fill (Sec. II.C) into vol_u8_dev / state_dev ([nz][ny][nx] bytes;
+ * state_dev may be NULL):
+ *   V = cnt ? min(255, floor((2 sum + cnt) / (2 cnt))) : 0, state MEASURED / EMPTY;
+ *   an EMPTY voxel with N >= fill_min MEASURED 26-neighbours (in grid) gets
+ *   floor((2 sum_N V + N) / (2 N)) and state FILLED (one pass over pre-fill values).
+ * region (nullable = whole grid): only voxels of region dilated by one voxel are
+ * written, which is exactly the set whose value can change when the accumulators
+ * change inside region; other output voxels are left untouched. */
+usv_status usv_finalize(usv_volume *vol, const usv_box *region, uint8_t *vol_u8_dev, uint8_t *state_dev);
+
+/* Bone depth + slab projection (Sec. II.D) of a finalized volume.  Outputs:
+ * depth_dev int16 [nz][nx]; mean_dev and max_dev FP32 [n_half][nz][nx].  n_half 1..4,
+ * half widths 0..255, k 1..64, r 0..8, y_lo >= 0, fallback_y in [0, ny). */
+usv_status usv_segment_project(usv_volume *vol, const usv_seg_params *params, const uint8_t *vol_u8_dev,
+                               const uint8_t *state_dev, int16_t *depth_dev, float *mean_dev, float *max_dev);
+
+/* ---------------------------------------------------------------------------------
+ * Batched multi-sweep ingest: n_sweeps independent (volume, probe, frames, poses)
+ * jobs compounded by one persistent launch on the first volume's stream.  All
+ * volumes must live on the same device.  Per sweep the result equals
+ * usv_ingest_frames on that sweep alone (bit for bit).  dirty_out: n_sweeps boxes or
+ * NULL.
+ * --------------------------------------------------------------------------------- */
+usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids, const uint8_t *const *frames_dev,
+                              const int64_t *row_pitch, const int64_t *frame_pitch,
+                              const double *const *poses_host, const int32_t *n_frames, int32_t n_sweeps,
+                              usv_box *dirty_out);
+
+/* Autotune the ingest tiling of a probe on sample data (n >= 1 frames) by timing
+ * every candidate on a scratch copy of the grid; the winner becomes the probe's
+ * tiling.  cache_path (nullable): results are read from / appended to this text
+ * file, keyed by device, image size, pixel/voxel ratio and mask.  Synchronous. */
+usv_status usv_autotune(usv_volume *vol, int32_t probe_id, const uint8_t *frames_dev, int64_t row_pitch,
+                        int64_t frame_pitch, const double *poses_host, int32_t n, const char *cache_path);
+
+/* Tile shape used for a probe: tile width/height in pixels (for reports). */
+usv_status usv_probe_tiling(const usv_volume *vol, int32_t probe_id, int32_t *tile_w, int32_t *tile_h);
+
+/* Force a probe's tile shape.  Supported shapes (w x h): 60x64, 64x48, 64x32, 32x64,
+ * 32x32, 64x16, 128x8, 48x60, 40x48; anything else is USV_E_UNSUPPORTED.  Results do
+ * not depend on the tiling (bit for bit), only the speed does. */
+usv_status usv_probe_set_tiling(usv_volume *vol, int32_t probe_id, int32_t tile_w, int32_t tile_h);
+
+/* ---------------------------------------------------------------------------------
+ * Real-time single-frame ingest through captured HIP graphs (Sec. II.C / III.B: one
+ * frame per grab at 30 fps).  usv_graph_create captures {host->device copy of one
+ * frame from pinned staging, host->device copy of its folded pose, PNN ingest of that
+ * frame} for a ring of staging slots.  usv_graph_launch copies frame_host (W*H bytes,
+ * row pitch W) and folds pose_host into the next slot and launches its graph on the
+ * volume's stream; the result equals usv_ingest_frames of that frame.
+ * --------------------------------------------------------------------------------- */
+usv_status usv_graph_create(usv_volume *vol, int32_t probe_id, usv_graph **out);
+usv_status usv_graph_launch(usv_graph *g, const uint8_t *frame_host, const double *pose_host, usv_box *dirty_out);
+usv_status usv_graph_destroy(usv_graph *g);
+
+/* ---------------------------------------------------------------------------------
+ * Differentiable trilinear splat (not in the paper; pose refinement against patient
+ * motion, cf. Sec. III.A).  Frame n uses T_n = Exp(xi_n) T*_n with xi = (rho [mm],
+ * omega [rad]) a left se(3) perturbation of the image->world pose T*_n (FP64 4x4).
+ * Pixel (u, v) -> voxel coordinate q = (T_n ((u+1/2) sx, (v+1/2) sy, 0, 1) - o) / s,
+ * p = q - 1/2, i0 = floor p, f = p - i0, corner weights prod_a (d_a ? f_a : 1 - f_a);
+ * out-of-grid corners are dropped.  Frames with even n feed set A, odd n set B:
+ * S_X += w I, W_X += w.  Volumes are FP32 [4][nz][ny][nx] in the order S_A, W_A, S_B,
+ * W_B.  All pointers are device memory; calls are ordered on the context's stream.
+ * --------------------------------------------------------------------------------- */
+usv_status usv_splat_create(const usv_grid_desc *grid, int32_t width, int32_t height, double sx, double sy,
+                            int32_t max_frames, void *stream, usv_splat **out);
+usv_status usv_splat_destroy(usv_splat *ctx);
+
+/* Forward: zeroes vols_dev and splats F frames of FP32 intensities I_dev [F][H][W]
+ * with poses Tstar_dev (F*16 FP64) and xi_dev (F*6 FP64). */
+usv_status usv_splat_forward(usv_splat *ctx, const float *I_dev, const double *Tstar_dev, const double *xi_dev,
+                             int32_t F, float *vols_dev);
+
+/* Overlap-consistency loss between the two frame sets: R = S_A W_B - S_B W_A,
+ * L = 1/2 sum R^2 (FP64 into loss_dev[0]); grads_dev (nullable, FP32 [4][nvox])
+ * receives dL/dS_A = R W_B, dL/dW_A = -R S_B, dL/dS_B = -R W_A, dL/dW_B = R S_A. */
+usv_status usv_overlap_loss(usv_splat *ctx, const float *vols_dev, double *loss_dev, float *grads_dev);
+
+/* Backward of any loss through the splat given grads_dev = dL/d(S_A, W_A, S_B, W_B)
+ * (FP32 [4][nvox]): dI_dev [F][H][W] FP32 receives dL/dI and dxi_dev [F][6] FP64
+ * receives dL/dxi = J_l(xi)^T (sum dL/dx, sum x cross dL/dx), with x the pixel's
+ * world point and J_l the SE(3) left Jacobian.  Weights are recomputed, not stored. */
+usv_status usv_splat_backward(usv_splat *ctx, const float *I_dev, const double *Tstar_dev, const double *xi_dev,
+                              int32_t F, const float *grads_dev, float *dI_dev, double *dxi_dev);
+
+/* ---------------------------------------------------------------------------------
+ * Host-only helpers (no device work; usable without a GPU)
+ * --------------------------------------------------------------------------------- */
+
+/* The FP32 pixel->voxel map the library uses for one pose: M[12] = 3 rows of
+ * (du, dv, 0, const). */
+usv_status usv_fold_pose(const usv_grid_desc *grid, const usv_probe_desc *probe, const double *pose, float *M12);
+
+/* The dirty box usv_ingest_frames reports for these poses (mask ignored). */
+usv_status usv_dirty_box(const usv_grid_desc *grid, const usv_probe_desc *probe, const double *poses, int32_t n,
+                         usv_box *out);
+
+/* Library version string. */
+const char *usv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* USV_H */

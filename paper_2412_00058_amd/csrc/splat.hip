@@ -1,0 +1,385 @@
+// Differentiable trilinear splat for gfx950 (beside the paper's PNN path; pose
+// refinement against patient motion).
+//   splat_pose_kernel    : per frame T = Exp(xi) T* (FP64, Rodrigues form), the FP64
+//                          pixel -> (voxel coordinate - 1/2) map and J_l(xi)^T (series
+//                          sum_k ad(xi)^k / (k+1)!);
+//   splat_fwd_kernel     : one block per 32x32 pixel tile; FP64 coordinates, FP32 corner
+//                          weights, merged in an LDS window of (S, W) pairs, flushed with
+//                          FP32 global atomics into the frame's set (even / odd frames);
+//   loss_kernel          : R = S_A W_B - S_B W_A, 1/2 sum R^2 (FP64 block partials) and
+//                          the four volume gradients;
+//   splat_bwd_kernel     : recomputes the weights, gathers the gradient volumes, writes
+//                          dL/dI and a per-tile FP64 partial of (sum dL/dq, sum (p - p_c)
+//                          x dL/dq);
+//   frame_reduce_kernel  : per frame, sums the tile partials in tile order (deterministic)
+//                          and applies J_l^T.
+#include "usv_internal.h"
+
+namespace usv {
+
+namespace {
+
+constexpr int STW = 32, STH = 32;
+constexpr int kSplatWin = 3072;   // (S, W) pairs per block: 24 KiB
+
+__device__ void mat3_mul(const double *a, const double *b, double *c) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) c[i * 3 + j] = a[i * 3] * b[j] + a[i * 3 + 1] * b[3 + j] + a[i * 3 + 2] * b[6 + j];
+}
+
+__global__ void splat_pose_kernel(SplatGeom g, const double *__restrict__ Tstar, const double *__restrict__ xi, int F,
+                                  double *__restrict__ Mq, double *__restrict__ Jt) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= F) return;
+  const double *x = xi + 6 * n;
+  const double w0 = x[3], w1 = x[4], w2 = x[5];
+  const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-3) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    A = sin(th) / th;
+    B = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double W[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+  double W2[9];
+  mat3_mul(W, W, W2);
+  double R[9], V[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    R[i] = I + A * W[i] + B * W2[i];
+    V[i] = I + B * W[i] + C * W2[i];
+  }
+  double t[3];
+  for (int i = 0; i < 3; ++i) t[i] = V[i * 3] * x[0] + V[i * 3 + 1] * x[1] + V[i * 3 + 2] * x[2];
+  const double *Ts = Tstar + 16 * n;
+  const double o[3] = {g.origin[0], g.origin[1], g.origin[2]};
+  for (int r = 0; r < 3; ++r) {
+    double T[4];
+    for (int c = 0; c < 4; ++c)
+      T[c] = R[r * 3] * Ts[c] + R[r * 3 + 1] * Ts[4 + c] + R[r * 3 + 2] * Ts[8 + c] + t[r] * Ts[12 + c];
+    // (x - o) / s - 1/2 as an affine map of the pixel index (u, v)
+    Mq[9 * n + 3 * r + 0] = T[0] * g.sx / g.s;
+    Mq[9 * n + 3 * r + 1] = T[1] * g.sy / g.s;
+    Mq[9 * n + 3 * r + 2] = (T[3] + 0.5 * g.sx * T[0] + 0.5 * g.sy * T[1] - o[r]) / g.s - 0.5;
+  }
+  // J_l(xi) = sum_k ad^k / (k+1)!, ad = [[w^, rho^], [0, w^]]
+  double ad[36] = {0};
+  const double P[9] = {0.0, -x[2], x[1], x[2], 0.0, -x[0], -x[1], x[0], 0.0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      ad[i * 6 + j] = W[i * 3 + j];
+      ad[i * 6 + 3 + j] = P[i * 3 + j];
+      ad[(3 + i) * 6 + 3 + j] = W[i * 3 + j];
+    }
+  double J[36], Pk[36], Q[36];
+  for (int i = 0; i < 36; ++i) {
+    Pk[i] = (i % 7 == 0) ? 1.0 : 0.0;
+    J[i] = Pk[i];
+  }
+  double fact = 1.0;
+  for (int k = 1; k <= 26; ++k) {
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < 6; ++l) acc += Pk[i * 6 + l] * ad[l * 6 + j];
+        Q[i * 6 + j] = acc;
+      }
+    fact *= (double)(k + 1);
+    for (int i = 0; i < 36; ++i) {
+      Pk[i] = Q[i];
+      J[i] += Q[i] / fact;
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) Jt[36 * n + i * 6 + j] = J[j * 6 + i];
+}
+
+// voxel window of a pixel tile: p is affine in (u, v), so its range over the tile is
+// reached at the corners picked by the coefficient signs (FP64 rounding is monotone).
+__device__ __forceinline__ bool splat_axis(const double *m, double u0, double u1, double v0, double v1, int n,
+                                           int &lo, int &hi) {
+  const double umin = m[0] >= 0.0 ? u0 : u1, umax = m[0] >= 0.0 ? u1 : u0;
+  const double vmin = m[1] >= 0.0 ? v0 : v1, vmax = m[1] >= 0.0 ? v1 : v0;
+  const double pmin = m[0] * umin + m[1] * vmin + m[2];
+  const double pmax = m[0] * umax + m[1] * vmax + m[2];
+  if (!(pmin == pmin) || !(pmax == pmax)) return false;
+  const double flo = floor(pmin), fhi = floor(pmax) + 1.0;
+  if (fhi < 0.0 || flo > (double)(n - 1)) return false;
+  lo = flo < 0.0 ? 0 : (int)flo;
+  hi = fhi > (double)(n - 1) ? n - 1 : (int)fhi;
+  return true;
+}
+
+struct PixW {
+  int i0[3];
+  float f[3];
+  bool ok0[3], ok1[3];
+};
+
+__device__ __forceinline__ void pixel_coord(const double *m, int u, int v, const SplatGeom &g, PixW &p, double pd[3]) {
+  const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double q = m[3 * r] * (double)u + m[3 * r + 1] * (double)v + m[3 * r + 2];
+    pd[r] = q;
+    const double fl = floor(q);
+    const int i = (fl > -2.0 && fl < 2.0e9) ? (int)fl : -2;
+    p.i0[r] = i;
+    p.f[r] = (float)(q - fl);
+    p.ok0[r] = i >= 0 && i < n[r];
+    p.ok1[r] = i + 1 >= 0 && i + 1 < n[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float *__restrict__ I,
+                                                        const double *__restrict__ Mq, float *__restrict__ vols) {
+  __shared__ __align__(16) float2 win[kSplatWin];
+  const int b = blockIdx.x;
+  const int tc = b % g.tiles_x, rest = b / g.tiles_x;
+  const int tr = rest % g.tiles_y, f = rest / g.tiles_y;
+  double m[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i] = Mq[9 * f + i];
+  const int u0 = tc * STW, v0 = tr * STH;
+  const int u1 = min(u0 + STW, g.W) - 1, v1 = min(v0 + STH, g.H) - 1;
+  int lo[3], hi[3];
+  const double du0 = u0, du1 = u1, dv0 = v0, dv1 = v1;
+  if (!splat_axis(m, du0, du1, dv0, dv1, g.nx, lo[0], hi[0])) return;
+  if (!splat_axis(m + 3, du0, du1, dv0, dv1, g.ny, lo[1], hi[1])) return;
+  if (!splat_axis(m + 6, du0, du1, dv0, dv1, g.nz, lo[2], hi[2])) return;
+  const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
+  const int64_t we64 = (int64_t)wx * wy * wz;
+  const bool direct = we64 > kSplatWin;
+  const int we = direct ? 0 : (int)we64;
+  const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+  float *S = vols + (int64_t)(f & 1) * 2 * nvox;
+  float *Wt = S + nvox;
+  for (int e = threadIdx.x; e < we; e += 256) win[e] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
+  const int u = u0 + tx;
+  for (int ty = ty0; ty < STH; ty += 8) {
+    const int v = v0 + ty;
+    if (u > u1 || v > v1) continue;
+    const float val = I[((int64_t)f * g.H + v) * g.W + u];
+    PixW p;
+    double pd[3];
+    pixel_coord(m, u, v, g, p, pd);
+#pragma unroll
+    for (int dlt = 0; dlt < 8; ++dlt) {
+      const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+      if (!(bx ? p.ok1[0] : p.ok0[0]) || !(by ? p.ok1[1] : p.ok0[1]) || !(bz ? p.ok1[2] : p.ok0[2])) continue;
+      const float w = (bx ? p.f[0] : 1.0f - p.f[0]) * (by ? p.f[1] : 1.0f - p.f[1]) * (bz ? p.f[2] : 1.0f - p.f[2]);
+      const int cx = p.i0[0] + bx, cy = p.i0[1] + by, cz = p.i0[2] + bz;
+      if (!direct) {
+        const int e = (cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2]));
+        atomicAdd(&win[e].x, w * val);
+        atomicAdd(&win[e].y, w);
+      } else {
+        const int64_t gi = (int64_t)cx + (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
+        atomicAdd(S + gi, w * val);
+        atomicAdd(Wt + gi, w);
+      }
+    }
+  }
+  __syncthreads();
+  if (direct) return;
+  const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
+  for (int e = threadIdx.x; e < we; e += 256) {
+    const float2 sw = win[e];
+    if (sw.x == 0.0f && sw.y == 0.0f) continue;
+    const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
+    const int ex = e - r1 * wx;
+    const int ez = wy == 1 ? r1 : (int)__umulhi((uint32_t)r1, mag_wy);
+    const int ey = r1 - ez * wy;
+    const int64_t gi = (int64_t)(lo[0] + ex) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
+    atomicAdd(S + gi, sw.x);
+    atomicAdd(Wt + gi, sw.y);
+  }
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(256) void loss_kernel(int64_t nvox, const float *__restrict__ vols, float *__restrict__ grads,
+                                                   double *__restrict__ partial) {
+  __shared__ double sh[4];
+  const float *SA = vols, *WA = vols + nvox, *SB = vols + 2 * nvox, *WB = vols + 3 * nvox;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nvox; i += (int64_t)gridDim.x * 256) {
+    const float sa = SA[i], wa = WA[i], sb = SB[i], wb = WB[i];
+    const float R = sa * wb - sb * wa;
+    acc += 0.5 * (double)R * (double)R;
+    if (grads) {
+      grads[i] = R * wb;
+      grads[nvox + i] = -R * sb;
+      grads[2 * nvox + i] = -R * wa;
+      grads[3 * nvox + i] = R * sa;
+    }
+  }
+  const double t = block_sum_d(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void sum_partials_kernel(const double *__restrict__ partial, int n, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += partial[i];
+    out[0] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float *__restrict__ I,
+                                                        const double *__restrict__ Mq, const float *__restrict__ grads,
+                                                        float *__restrict__ dI, double *__restrict__ partial) {
+  __shared__ float red[6][4];
+  const int b = blockIdx.x;
+  const int tc = b % g.tiles_x, rest = b / g.tiles_x;
+  const int tr = rest % g.tiles_y, f = rest / g.tiles_y;
+  double m[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i] = Mq[9 * f + i];
+  const double uc = 0.5 * (double)(g.W - 1), vc = 0.5 * (double)(g.H - 1);
+  double pc[3];
+  for (int r = 0; r < 3; ++r) pc[r] = m[3 * r] * uc + m[3 * r + 1] * vc + m[3 * r + 2];
+  const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+  const float *GS = grads + (int64_t)(f & 1) * 2 * nvox;
+  const float *GW = GS + nvox;
+  const int u0 = tc * STW, v0 = tr * STH;
+  const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
+  const int u = u0 + tx;
+  float acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int ty = ty0; ty < STH; ty += 8) {
+    const int v = v0 + ty;
+    if (u >= g.W || v >= g.H) continue;
+    const int64_t pix = ((int64_t)f * g.H + v) * g.W + u;
+    const float val = I[pix];
+    PixW p;
+    double pd[3];
+    pixel_coord(m, u, v, g, p, pd);
+    float di = 0.0f, gq[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int dlt = 0; dlt < 8; ++dlt) {
+      const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+      if (!(bx ? p.ok1[0] : p.ok0[0]) || !(by ? p.ok1[1] : p.ok0[1]) || !(bz ? p.ok1[2] : p.ok0[2])) continue;
+      const float fx = bx ? p.f[0] : 1.0f - p.f[0];
+      const float fy = by ? p.f[1] : 1.0f - p.f[1];
+      const float fz = bz ? p.f[2] : 1.0f - p.f[2];
+      const int64_t gi = (int64_t)(p.i0[0] + bx) + (int64_t)g.nx * ((int64_t)(p.i0[1] + by) + (int64_t)g.ny * (p.i0[2] + bz));
+      const float gs = GS[gi], gw = GW[gi];
+      di += fx * fy * fz * gs;
+      const float coef = val * gs + gw;
+      gq[0] += coef * (bx ? 1.0f : -1.0f) * fy * fz;
+      gq[1] += coef * (by ? 1.0f : -1.0f) * fx * fz;
+      gq[2] += coef * (bz ? 1.0f : -1.0f) * fx * fy;
+    }
+    dI[pix] = di;
+    const float rx = (float)(pd[0] - pc[0]), ry = (float)(pd[1] - pc[1]), rz = (float)(pd[2] - pc[2]);
+    acc[0] += gq[0];
+    acc[1] += gq[1];
+    acc[2] += gq[2];
+    acc[3] += ry * gq[2] - rz * gq[1];
+    acc[4] += rz * gq[0] - rx * gq[2];
+    acc[5] += rx * gq[1] - ry * gq[0];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    const double t = (double)red[k][0] + (double)red[k][1] + (double)red[k][2] + (double)red[k][3];
+    partial[(int64_t)b * 6 + k] = t;
+  }
+}
+
+__global__ void frame_reduce_kernel(SplatGeom g, const double *__restrict__ Mq, const double *__restrict__ Jt,
+                                    const double *__restrict__ partial, int F, double *__restrict__ dxi) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int tiles = g.tiles_x * g.tiles_y;
+  double sg[3] = {0, 0, 0}, sm[3] = {0, 0, 0};
+  for (int t = 0; t < tiles; ++t) {
+    const double *p = partial + ((int64_t)f * tiles + t) * 6;
+    sg[0] += p[0];
+    sg[1] += p[1];
+    sg[2] += p[2];
+    sm[0] += p[3];
+    sm[1] += p[4];
+    sm[2] += p[5];
+  }
+  const double *m = Mq + 9 * f;
+  const double uc = 0.5 * (double)(g.W - 1), vc = 0.5 * (double)(g.H - 1);
+  double c[3], gx[3];
+  for (int r = 0; r < 3; ++r) {
+    c[r] = g.origin[r] + g.s * (m[3 * r] * uc + m[3 * r + 1] * vc + m[3 * r + 2] + 0.5);   // frame centre (mm)
+    gx[r] = sg[r] / g.s;                                                                   // sum dL/dx
+  }
+  // dL/deps = (sum dL/dx, sum (x - c) x dL/dx + c x sum dL/dx); (x - c) x dL/dx = (p - p_c) x dL/dq
+  double de[6] = {gx[0], gx[1], gx[2], sm[0] + c[1] * gx[2] - c[2] * gx[1], sm[1] + c[2] * gx[0] - c[0] * gx[2],
+                  sm[2] + c[0] * gx[1] - c[1] * gx[0]};
+  const double *J = Jt + 36 * f;
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < 6; ++j) acc += J[i * 6 + j] * de[j];
+    dxi[6 * f + i] = acc;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_splat_pose(const SplatGeom &g, const double *Tstar, const double *xi, int F, double *Mq, double *Jt,
+                             hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  hipLaunchKernelGGL(splat_pose_kernel, dim3((F + 63) / 64), dim3(64), 0, s, g, Tstar, xi, F, Mq, Jt);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat_forward(const SplatGeom &g, const float *I, const double *Mq, int F, float *vols,
+                                hipStream_t s) {
+  const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+  hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(vols), 4 * nvox, s);
+  if (e != hipSuccess || F <= 0) return e;
+  const int blocks = F * g.tiles_x * g.tiles_y;
+  hipLaunchKernelGGL(splat_fwd_kernel, dim3(blocks), dim3(256), 0, s, g, I, Mq, vols);
+  return hipGetLastError();
+}
+
+hipError_t launch_overlap_loss(int64_t nvox, const float *vols, float *grads, double *partial, int n_partial,
+                               double *loss, hipStream_t s) {
+  hipLaunchKernelGGL(loss_kernel, dim3(n_partial), dim3(256), 0, s, nvox, vols, grads, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partial, n_partial, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat_backward(const SplatGeom &g, const float *I, const double *Mq, const double *Jt, int F,
+                                 const float *grads, float *dI, double *partial, double *dxi, hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  const int blocks = F * g.tiles_x * g.tiles_y;
+  hipLaunchKernelGGL(splat_bwd_kernel, dim3(blocks), dim3(256), 0, s, g, I, Mq, grads, dI, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(frame_reduce_kernel, dim3((F + 63) / 64), dim3(64), 0, s, g, Mq, Jt, partial, F, dxi);
+  return hipGetLastError();
+}
+
+}  // namespace usv

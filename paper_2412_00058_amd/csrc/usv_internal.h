@@ -1,0 +1,122 @@
+// Internal declarations of the usv library (kernels + host runtime).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace usv {
+
+// ---- nearest-voxel ingest --------------------------------------------------------------
+
+constexpr int kBlock = 256;          // threads per ingest block (4 waves of 64)
+constexpr int kWinMax = 6144;        // LDS voxel-window entries per block (24 KiB)
+constexpr int kMaxTileRows = 64;     // rows of a tile (per-row constant table)
+constexpr int kMaxTilePixels = 4095; // window entries pack (count << 20 | sum): count < 4096
+constexpr int kLaunchFrames = 64;    // frames whose maps travel in one launch's arguments
+
+// Tiling of one probe's images: a tile is tw = 4*lr columns by th = 4*rpw*kr rows,
+// rpw = 64 / lr row groups per wave.
+struct Tiling {
+  int32_t tw, th, lr, kr, rpw, tiles_x, tiles_y;
+  uint32_t lr_magic;   // 2^32 / lr + 1: lane / lr == umulhi(lane, lr_magic) for lane < 64
+};
+
+// Everything one ingest job (one volume + one probe + its frames) needs on the device.
+struct SweepDesc {
+  const uint8_t *frames;
+  int64_t frame_pitch, row_pitch;
+  uint32_t *sum;           // uint32 [nvox]
+  uint32_t *cnt32;         // uint16 [nvox] viewed as 32-bit words (2 voxels per word)
+  uint32_t *err;           // [0]: count overflow seen
+  const uint32_t *spans;   // per row (lo | hi << 16) of a row-convex mask, or null
+  const uint8_t *mask;     // general H*W mask, or null
+  const uint8_t *tile_class;  // [tiles_y][tiles_x]: 0 inside mask, 1 partial, 2 outside; null = all 0
+  int32_t W, H;
+  int32_t nx, ny, nz;
+  uint32_t nxb, nyb, nzb;  // bit patterns of (float)nx, (float)ny, (float)nz
+  Tiling t;
+};
+
+// Arguments of the plain (per-call) ingest launch: the folded maps of up to
+// kLaunchFrames frames travel in the kernel argument segment.
+struct IngestLaunch {
+  SweepDesc d;
+  int32_t n_frames;
+  int32_t fidx[kLaunchFrames];     // frame index in the caller's buffer
+  float M[kLaunchFrames][9];       // per frame: rows r = (du, dv, const)
+};
+
+// Batched persistent ingest: a flat list of (sweep, frame, tile) items.
+struct BatchSweep {
+  SweepDesc d;
+  const float *M;          // [n_frames][9] device
+  const int32_t *fidx;     // [n_frames] device
+  int32_t n_frames;
+  int64_t item_begin;      // first item of this sweep in the flat list
+  int64_t items_per_frame;
+};
+
+struct BatchLaunch {
+  const BatchSweep *sweeps;   // device array
+  int32_t n_sweeps;
+  int64_t n_items;
+  int32_t items_per_pull;
+  uint32_t *counter;          // device work counter (zeroed before launch)
+};
+
+hipError_t launch_ingest(const IngestLaunch &a, int n_blocks, hipStream_t s);
+hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t s);
+hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t *fidx, int n_frames, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int64_t n_words, hipStream_t s);
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n_words, hipStream_t s);
+
+// ---- finalize ----------------------------------------------------------------------------
+
+struct FinalizeArgs {
+  const uint32_t *sum;
+  const uint16_t *cnt;
+  uint8_t *V;
+  uint8_t *state;        // may be null
+  int32_t nx, ny, nz;
+  int32_t fill_min;
+  int32_t lo[3], hi[3];  // output box [lo, hi) (already dilated and clipped)
+  int32_t zchunk;
+};
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+
+// ---- segmentation + projection -------------------------------------------------------------
+
+struct SegArgs {
+  const uint8_t *V;
+  const uint8_t *state;
+  int16_t *raw;           // scratch [nz][nx]
+  int16_t *depth;
+  float *mean, *max;
+  int32_t nx, ny, nz;
+  int32_t mode, y_lo, k, tau_I, tau_G, r, fallback_y, n_half;
+  int32_t half[4];
+  double K, D_mm, L_mm, z1_mm, yref_mm;
+  double origin_y, origin_z, s;
+};
+hipError_t launch_segment(const SegArgs &a, hipStream_t s);
+
+// ---- differentiable splat ------------------------------------------------------------------
+
+struct SplatGeom {
+  int32_t nx, ny, nz;
+  double origin[3];
+  double s;
+  int32_t W, H;
+  double sx, sy;
+  int32_t tiles_x, tiles_y;   // 32x32-pixel tiles per frame
+};
+hipError_t launch_splat_pose(const SplatGeom &g, const double *Tstar, const double *xi, int F, double *Mq,
+                             double *Jt, hipStream_t s);
+hipError_t launch_splat_forward(const SplatGeom &g, const float *I, const double *Mq, int F, float *vols,
+                                hipStream_t s);
+hipError_t launch_overlap_loss(int64_t nvox, const float *vols, float *grads, double *partial, int n_partial,
+                               double *loss, hipStream_t s);
+hipError_t launch_splat_backward(const SplatGeom &g, const float *I, const double *Mq, const double *Jt, int F,
+                                 const float *grads, float *dI, double *partial, double *dxi, hipStream_t s);
+
+}  // namespace usv

@@ -1,0 +1,348 @@
+"""Python binding of the usv C ABI: argument marshalling only.
+
+Torch supplies device memory and the HIP stream (the current torch stream at object
+creation); every step of the compounding path runs in libusv.so's HIP kernels.  There
+is no CPU path: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from ._lib import Box, GridDesc, ProbeDesc, SegParams, UsvError, check, lib
+
+SEG_ALG2, SEG_ALG1, SEG_FIXED = 0, 1, 2
+EMPTY, MEASURED, FILLED = 0, 1, 2
+
+
+def _vp(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream_ptr() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def grid_desc(dims, origin_mm=(0.0, 0.0, 0.0), voxel_mm=0.5, fill_min=1) -> GridDesc:
+    g = GridDesc()
+    for a in range(3):
+        g.dims[a] = int(dims[a])
+        g.origin_mm[a] = float(origin_mm[a])
+    g.voxel_mm = float(voxel_mm)
+    g.fill_min = int(fill_min)
+    return g
+
+
+def probe_desc(width, height, pixel_mm, calib=None, mask=None):
+    """Returns (ProbeDesc, keepalive) -- the mask buffer must outlive the add_probe call."""
+    p = ProbeDesc()
+    p.width, p.height = int(width), int(height)
+    p.pixel_mm[0], p.pixel_mm[1] = float(pixel_mm[0]), float(pixel_mm[1])
+    cal = np.eye(4) if calib is None else np.asarray(calib, dtype=np.float64).reshape(4, 4)
+    for i in range(16):
+        p.calib[i] = float(cal.ravel()[i])
+    keep = None
+    if mask is not None:
+        keep = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert keep.shape == (height, width)
+        p.mask_host = keep.ctypes.data
+    else:
+        p.mask_host = None
+    return p, keep
+
+
+def seg_params(mode=SEG_ALG2, y_lo=0, k=6, tau_I=128, tau_G=40, r=2, fallback_y=0, half=(2, 5, 10),
+               K=0.04, D_mm=35.0, L_mm=560.0, z1_mm=0.0, yref_mm=0.0) -> SegParams:
+    p = SegParams()
+    p.mode, p.y_lo, p.k, p.tau_I, p.tau_G, p.r, p.fallback_y = mode, y_lo, k, tau_I, tau_G, r, fallback_y
+    p.n_half = len(half)
+    for i, h in enumerate(half):
+        p.half[i] = int(h)
+    p.K, p.D_mm, p.L_mm, p.z1_mm, p.yref_mm = K, D_mm, L_mm, z1_mm, yref_mm
+    return p
+
+
+def _poses(poses) -> np.ndarray:
+    a = np.ascontiguousarray(poses, dtype=np.float64)
+    return a.reshape(-1, 16)
+
+
+def accumulator_bytes(dims) -> int:
+    return int(lib().usv_accumulator_bytes(C.byref(grid_desc(dims))))
+
+
+class Volume:
+    """Persistent incremental reconstruction (uint32 sum + uint16 count per voxel)."""
+
+    def __init__(self, dims, origin_mm=(0.0, 0.0, 0.0), voxel_mm=0.5, fill_min=1, device="cuda"):
+        L = lib()
+        self.dims = tuple(int(d) for d in dims)
+        self.desc = grid_desc(self.dims, origin_mm, voxel_mm, fill_min)
+        nbytes = int(L.usv_accumulator_bytes(C.byref(self.desc)))
+        if nbytes == 0:
+            raise UsvError(-1, "invalid grid")
+        self.nvox = self.dims[0] * self.dims[1] * self.dims[2]
+        self.acc = torch.empty(nbytes // 4, dtype=torch.int32, device=device)
+        self.stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        check(L.usv_create_volume(C.byref(self.desc), _vp(self.acc), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().usv_destroy_volume(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # accumulators as torch views
+    @property
+    def sum(self):
+        return self.acc[: self.nvox].view(torch.int32)
+
+    @property
+    def cnt(self):
+        return self.acc.view(torch.int16)[2 * self.nvox: 2 * self.nvox + self.nvox]
+
+    def add_probe(self, width, height, pixel_mm, calib=None, mask=None) -> int:
+        p, keep = probe_desc(width, height, pixel_mm, calib, mask)
+        pid = C.c_int32()
+        check(lib().usv_add_probe(self.h, C.byref(p), C.byref(pid)), self.h)
+        return pid.value
+
+    def tiling(self, probe_id):
+        w, h = C.c_int32(), C.c_int32()
+        check(lib().usv_probe_tiling(self.h, probe_id, C.byref(w), C.byref(h)), self.h)
+        return w.value, h.value
+
+    def set_tiling(self, probe_id, tile_w, tile_h):
+        check(lib().usv_probe_set_tiling(self.h, probe_id, int(tile_w), int(tile_h)), self.h)
+
+    def ingest(self, probe_id, frames: torch.Tensor, poses) -> Box:
+        """frames: uint8 device tensor [F, H, W] (row pitch = stride); poses [F, 4, 4] FP64 host."""
+        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3
+        assert frames.stride(2) == 1
+        P = _poses(poses)
+        n = frames.shape[0]
+        assert P.shape[0] == n
+        box = Box()
+        check(lib().usv_ingest_frames(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
+                                      P.ctypes.data_as(C.c_void_p), n, C.byref(box)), self.h)
+        return box
+
+    def finalize(self, region: Optional[Box] = None, out=None, with_state=True):
+        nx, ny, nz = self.dims
+        if out is None:
+            V = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.acc.device)
+            S = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.acc.device) if with_state else None
+        else:
+            V, S = out
+        check(lib().usv_finalize(self.h, C.byref(region) if region is not None else None, _vp(V), _vp(S)), self.h)
+        return V, S
+
+    def segment_project(self, params: SegParams, V, S, out=None):
+        nx, ny, nz = self.dims
+        if out is None:
+            depth = torch.empty((nz, nx), dtype=torch.int16, device=V.device)
+            mean = torch.empty((params.n_half, nz, nx), dtype=torch.float32, device=V.device)
+            mx = torch.empty((params.n_half, nz, nx), dtype=torch.float32, device=V.device)
+        else:
+            depth, mean, mx = out
+        check(lib().usv_segment_project(self.h, C.byref(params), _vp(V), _vp(S), _vp(depth), _vp(mean), _vp(mx)),
+              self.h)
+        return depth, mean, mx
+
+    def sync(self):
+        check(lib().usv_sync(self.h), self.h)
+
+    def status(self) -> int:
+        return int(lib().usv_sync(self.h))
+
+    def reset(self):
+        check(lib().usv_reset(self.h), self.h)
+
+    def export_accumulators(self, dst: Optional[torch.Tensor] = None) -> torch.Tensor:
+        dst = torch.empty_like(self.acc) if dst is None else dst
+        check(lib().usv_export_accumulators(self.h, _vp(dst)), self.h)
+        return dst
+
+    def import_accumulators(self, src: torch.Tensor):
+        check(lib().usv_import_accumulators(self.h, _vp(src)), self.h)
+
+    def autotune(self, probe_id, frames: torch.Tensor, poses, cache_path: Optional[str] = None):
+        P = _poses(poses)
+        check(lib().usv_autotune(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
+                                 P.ctypes.data_as(C.c_void_p), frames.shape[0],
+                                 cache_path.encode() if cache_path else None), self.h)
+        return self.tiling(probe_id)
+
+    def host_accumulators(self):
+        """(sum uint32 [nvox], cnt uint16 [nvox]) copied to the host (synchronises)."""
+        a = self.acc.cpu().numpy()
+        s = a[: self.nvox].view(np.uint32).copy()
+        c = a.view(np.uint16)[2 * self.nvox: 3 * self.nvox].copy()
+        return s, c
+
+
+def ingest_batched(jobs: Sequence[tuple]):
+    """jobs: sequence of (Volume, probe_id, frames uint8 [F,H,W] device tensor, poses [F,4,4]).
+    One persistent launch on the first volume's stream.  Returns the dirty boxes."""
+    n = len(jobs)
+    L = lib()
+    vols = (C.c_void_p * n)(*[j[0].h for j in jobs])
+    pids = (C.c_int32 * n)(*[int(j[1]) for j in jobs])
+    frames = (C.c_void_p * n)(*[j[2].data_ptr() for j in jobs])
+    rp = (C.c_int64 * n)(*[j[2].stride(1) for j in jobs])
+    fp = (C.c_int64 * n)(*[j[2].stride(0) for j in jobs])
+    P = [_poses(j[3]) for j in jobs]
+    pp = (C.c_void_p * n)(*[p.ctypes.data for p in P])
+    nf = (C.c_int32 * n)(*[int(j[2].shape[0]) for j in jobs])
+    boxes = (Box * n)()
+    check(L.usv_ingest_batched(vols, pids, frames, rp, fp, pp, nf, n, boxes), jobs[0][0].h)
+    return list(boxes)
+
+
+class Graph:
+    """Captured single-frame ingest (pinned staging slots + H2D copies + PNN kernel)."""
+
+    def __init__(self, vol: Volume, probe_id: int):
+        h = C.c_void_p()
+        check(lib().usv_graph_create(vol.h, probe_id, C.byref(h)), vol.h)
+        self.h = h
+        self.vol = vol
+
+    def launch(self, frame_host: np.ndarray, pose) -> Box:
+        f = np.ascontiguousarray(frame_host, dtype=np.uint8)
+        P = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+        box = Box()
+        check(lib().usv_graph_launch(self.h, f.ctypes.data_as(C.c_void_p), P.ctypes.data_as(C.c_void_p),
+                                     C.byref(box)), self.vol.h)
+        return box
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().usv_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --- host-only helpers ------------------------------------------------------------------
+
+
+def fold_pose(dims, origin_mm, voxel_mm, width, height, pixel_mm, calib, pose) -> np.ndarray:
+    """The library's FP32 pixel -> voxel map for one pose, as [3][4] (du, dv, 0, const)."""
+    g = grid_desc(dims, origin_mm, voxel_mm)
+    p, _ = probe_desc(width, height, pixel_mm, calib)
+    P = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+    M = np.zeros(12, dtype=np.float32)
+    check(lib().usv_fold_pose(C.byref(g), C.byref(p), P.ctypes.data_as(C.c_void_p), M.ctypes.data_as(C.c_void_p)))
+    return M.reshape(3, 4)
+
+
+def dirty_box(dims, origin_mm, voxel_mm, width, height, pixel_mm, calib, poses) -> Box:
+    g = grid_desc(dims, origin_mm, voxel_mm)
+    p, _ = probe_desc(width, height, pixel_mm, calib)
+    P = _poses(poses)
+    b = Box()
+    check(lib().usv_dirty_box(C.byref(g), C.byref(p), P.ctypes.data_as(C.c_void_p), P.shape[0], C.byref(b)))
+    return b
+
+
+def version() -> str:
+    return lib().usv_version().decode()
+
+
+# --- differentiable splat -------------------------------------------------------------------
+
+
+class SplatContext:
+    """Geometry + scratch of the trilinear splat on the current torch stream."""
+
+    def __init__(self, dims, origin_mm, voxel_mm, width, height, pixel_mm, max_frames):
+        g = grid_desc(dims, origin_mm, voxel_mm)
+        h = C.c_void_p()
+        check(lib().usv_splat_create(C.byref(g), int(width), int(height), float(pixel_mm[0]), float(pixel_mm[1]),
+                                     int(max_frames), _stream_ptr(), C.byref(h)))
+        self.h = h
+        self.dims = tuple(int(d) for d in dims)
+        self.nvox = self.dims[0] * self.dims[1] * self.dims[2]
+        self.W, self.H = int(width), int(height)
+
+    def forward(self, I, Tstar, xi, vols=None):
+        F = I.shape[0]
+        vols = torch.empty((4, self.nvox), dtype=torch.float32, device=I.device) if vols is None else vols
+        check(lib().usv_splat_forward(self.h, _vp(I), _vp(Tstar), _vp(xi), F, _vp(vols)))
+        return vols
+
+    def loss(self, vols, want_grads=True):
+        loss = torch.empty(1, dtype=torch.float64, device=vols.device)
+        grads = torch.empty_like(vols) if want_grads else None
+        check(lib().usv_overlap_loss(self.h, _vp(vols), _vp(loss), _vp(grads)))
+        return loss, grads
+
+    def backward(self, I, Tstar, xi, grads, dI=None, dxi=None):
+        F = I.shape[0]
+        dI = torch.empty_like(I) if dI is None else dI
+        dxi = torch.empty((F, 6), dtype=torch.float64, device=I.device) if dxi is None else dxi
+        check(lib().usv_splat_backward(self.h, _vp(I), _vp(Tstar), _vp(xi), F, _vp(grads), _vp(dI), _vp(dxi)))
+        return dI, dxi
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().usv_splat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SplatFn(torch.autograd.Function):
+    """vols = SplatFn.apply(ctx, I [F,H,W] fp32, xi [F,6] fp64, Tstar [F,4,4] fp64) -> [4, nvox]
+    (S_A, W_A, S_B, W_B).  Backward recomputes the weights in the HIP kernel."""
+
+    @staticmethod
+    def forward(fctx, sctx: SplatContext, I, xi, Tstar):
+        I = I.contiguous()
+        xi = xi.contiguous()
+        Tstar = Tstar.contiguous()
+        vols = sctx.forward(I, Tstar, xi)
+        fctx.sctx = sctx
+        fctx.save_for_backward(I, xi, Tstar)
+        return vols
+
+    @staticmethod
+    def backward(fctx, gvols):
+        I, xi, Tstar = fctx.saved_tensors
+        dI, dxi = fctx.sctx.backward(I, Tstar, xi, gvols.contiguous().float())
+        return None, dI, dxi, None
+
+
+class OverlapLossFn(torch.autograd.Function):
+    """L = 1/2 sum (S_A W_B - S_B W_A)^2 over the four splat volumes (FP64 scalar)."""
+
+    @staticmethod
+    def forward(fctx, sctx: SplatContext, vols):
+        loss, grads = sctx.loss(vols, want_grads=True)
+        fctx.save_for_backward(grads)
+        return loss[0]
+
+    @staticmethod
+    def backward(fctx, gl):
+        (grads,) = fctx.saved_tensors
+        return None, grads * gl.to(grads.dtype)
