@@ -1,0 +1,342 @@
+"""Benchmark of the compounding hot path on one MI355X.
+
+One step = one whole-spine sweep through the full path: zero the accumulators,
+compound 3600 frames (480 x 640 uint8, 0.1 mm pixels, 560 mm path, i.i.d. +-5 deg
+jitter) into a 400 x 240 x 1120 grid at 0.5 mm in 57 calls of <= 64 frames, normalise +
+hole fill the whole grid, then ALG2 depth map + slab mean/max projections (h = 2, 5, 10).
+Inputs are synthetic and already resident in HBM when the timed region starts.
+
+Prints one JSON line.  `value` = frames/s of the whole step.  `roofline` covers the
+dominant kernel (the PNN ingest): algorithmic bytes per launch (pixels + maps + 12 bytes
+of accumulator read/write per distinct voxel touched by the launch, counted by the CPU
+oracle) divided by the launch duration measured with HIP events on the library's stream.
+`cpu_baseline` times the CPU oracle on the same step on one host core.
+Beside the main line: differentiable splat forward+backward frames/s (512 frames of
+320 x 240 into 256 x 192 x 512) and batched 16-sweep ingest frames/s.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s compounded into 0.5 mm voxel grid; % HBM roofline; fwd+bwd frames/s"
+HBM_PEAK_GBS = 8000.0
+CHUNK = 64
+SEG = dict(y_lo=40, k=6, tau_I=128, tau_G=40, r=2, fallback_y=74, half=(2, 5, 10))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+_SWEEP = None
+
+
+def _distinct_worker(q):
+    """Oracle pass over the whole sweep counting, per 64-frame call, the kept pixels and the
+    distinct voxels touched (the accumulator traffic a perfect merge still has to move)."""
+    import oracle
+    d = _SWEEP
+    acc = oracle.Accum(d["grid"])
+    out = []
+    for c in range(0, d["frames"].shape[0], CHUNK):
+        kept, U = acc.ingest(d["frames"][c:c + CHUNK], d["poses"][c:c + CHUNK], d["probe"], count_distinct=True)
+        out.append((kept, U))
+    q.put(out)
+
+
+def time_oracle_step(d, seg):
+    """CPU baseline: the oracle as it stands, same step, one host thread."""
+    import oracle
+    t0 = time.perf_counter()
+    acc = oracle.Accum(d["grid"])
+    for c in range(0, d["frames"].shape[0], CHUNK):
+        acc.ingest(d["frames"][c:c + CHUNK], d["poses"][c:c + CHUNK], d["probe"])
+    V, S, _ = oracle.finalize(d["grid"], acc.sum, acc.cnt)
+    oracle.segment(d["grid"], V, S, oracle.seg_params(mode=oracle.ALG2, **seg))
+    return time.perf_counter() - t0
+
+
+def traffic_from_profile(src_hash):
+    """HBM traffic per ingest launch from the committed rocprofv3 counter summary, if it was
+    taken on the current ingest kernel source; otherwise None."""
+    p = os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json")
+    try:
+        rec = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if rec.get("ingest_source_sha256") != src_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def ingest_source_hash():
+    h = hashlib.sha256()
+    for f in ("ingest.hip", "usv_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2412_00058_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def bench_splat(torch, usv, steps):
+    import synth
+    d = synth.cfg5()
+    g = d["grid"]
+    F = d["I"].shape[0]
+    ctx = usv.SplatContext(g.dims, g.origin_mm, g.voxel_mm, d["probe"].width, d["probe"].height,
+                           d["probe"].pixel_mm, F)
+    I = torch.from_numpy(d["I"]).cuda()
+    T = torch.from_numpy(d["Tstar"]).cuda()
+    xi = torch.from_numpy(d["xi"]).cuda()
+    vols = torch.empty((4, g.nvox), dtype=torch.float32, device="cuda")
+    grads = torch.empty_like(vols)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    dI = torch.empty_like(I)
+    dxi = torch.empty((F, 6), dtype=torch.float64, device="cuda")
+    L = usv.lib()
+    vp = lambda t: C.c_void_p(t.data_ptr())
+
+    def step():
+        L.usv_splat_forward(ctx.h, vp(I), vp(T), vp(xi), F, vp(vols))
+        L.usv_overlap_loss(ctx.h, vp(vols), vp(loss), vp(grads))
+        L.usv_splat_backward(ctx.h, vp(I), vp(T), vp(xi), F, vp(grads), vp(dI), vp(dxi))
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ctx.close()
+    return F / dt, dt * 1e3
+
+
+def bench_batched(torch, usv, steps):
+    import synth
+    plan = synth.cfg4_plan()
+    banks = {True: synth.frame_bank(True), False: synth.frame_bank(False)}
+    jobs = []
+    total = 0
+    for sw in plan:
+        p, g = sw["probe"], sw["grid"]
+        vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+        pid = vol.add_probe(p.width, p.height, p.pixel_mm, None, p.mask)
+        bank = torch.from_numpy(banks[sw["linear"]]).cuda()
+        F = sw["F"]
+        fr = torch.empty((F, p.height, p.width), dtype=torch.uint8, device="cuda")
+        for k in range(0, F, bank.shape[0]):
+            n = min(bank.shape[0], F - k)
+            fr[k:k + n] = bank[:n]
+        jobs.append((vol, pid, fr, sw["poses"]))
+        total += F
+    usv.ingest_batched(jobs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for j in jobs:
+            j[0].reset()
+        usv.ingest_batched(jobs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    for j in jobs:
+        if j[0].status() != 0:
+            raise RuntimeError("batched ingest reported an error")
+    return total / dt, dt * 1e3, total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the splat and batched lines")
+    ap.add_argument("--profile-pass", action="store_true", help="one short pass for rocprofv3 (no oracle, no extras)")
+    ap.add_argument("--cache", default=None,
+                    help="load the generated sweep from this .npz (written there if missing); lets a profiled "
+                         "run skip the generator's worker processes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build is single-GPU only (see DESIGN.md, sharding plan)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    global _SWEEP
+    import synth
+    print("[bench] generating whole-spine sweep", file=sys.stderr, flush=True)
+    t_gen = time.perf_counter()
+    if args.cache and os.path.exists(args.cache):
+        z = np.load(args.cache, allow_pickle=False)
+        d = synth.cfg2(count=0)
+        d["frames"], d["poses"] = z["frames"], z["poses"]
+    else:
+        d = synth.cfg2()
+        if args.cache:
+            np.savez(args.cache, frames=d["frames"], poses=d["poses"])
+    print("[bench] generated in %.1f s" % (time.perf_counter() - t_gen), file=sys.stderr, flush=True)
+
+    # the oracle's distinct-voxel pass runs in a child forked before any GPU call
+    q = None
+    proc = None
+    if not args.profile_pass:
+        _SWEEP = d
+        ctx = mp.get_context("fork")
+        q = ctx.Queue()
+        proc = ctx.Process(target=_distinct_worker, args=(q,), daemon=True)
+        proc.start()
+
+    import torch
+    import paper_2412_00058_amd as usv
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    g, p = d["grid"], d["probe"]
+    F = d["frames"].shape[0]
+    frames = torch.from_numpy(d["frames"]).cuda()
+    vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+    pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+    tile = vol.tiling(pid)
+    nx, ny, nz = g.dims
+    V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    S = torch.empty_like(V)
+    prm = usv.seg_params(mode=usv.SEG_ALG2, **SEG)
+    dep = torch.empty((nz, nx), dtype=torch.int16, device="cuda")
+    mean = torch.empty((3, nz, nx), dtype=torch.float32, device="cuda")
+    mx = torch.empty_like(mean)
+    L = usv.lib()
+    chunks = []
+    for c in range(0, F, CHUNK):
+        n = min(CHUNK, F - c)
+        P = np.ascontiguousarray(d["poses"][c:c + n].reshape(n, 16))
+        chunks.append((C.c_void_p(frames[c].data_ptr()), P, P.ctypes.data_as(C.c_void_p), n))
+    rp, fp = frames.stride(1), frames.stride(0)
+    Vp, Sp = C.c_void_p(V.data_ptr()), C.c_void_p(S.data_ptr())
+    outs = [C.c_void_p(t.data_ptr()) for t in (dep, mean, mx)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    n_launch = len(chunks)
+
+    host_submit = []
+
+    def step(times=None):
+        vol.reset()
+        if times is not None:
+            ev[0].record()
+        th = time.perf_counter()
+        for fptr, _, pptr, n in chunks:
+            st = L.usv_ingest_frames(vol.h, pid, fptr, rp, fp, pptr, n, None)
+            if st != 0:
+                raise RuntimeError("ingest failed: %d" % st)
+        host_submit.append(time.perf_counter() - th)
+        if times is not None:
+            ev[1].record()
+        L.usv_finalize(vol.h, None, Vp, Sp)
+        if times is not None:
+            ev[2].record()
+        L.usv_segment_project(vol.h, C.byref(prm), Vp, Sp, *outs)
+        if times is not None:
+            ev[3].record()
+            times.append(ev)
+
+    for _ in range(max(args.warmup, 0 if args.profile_pass else 1)):
+        step()
+    torch.cuda.synchronize()
+    steps = 1 if args.profile_pass else args.steps
+    phase = np.zeros(3)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tl = []
+        step(tl)
+        ev[3].synchronize()   # this step's events are read before the next step re-records them
+        phase += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = vol.status()
+    if st != 0:
+        raise RuntimeError("volume status %d after the timed steps" % st)
+    ms_step = (t1 - t0) * 1e3 / steps
+    phase /= steps
+    value = F / (ms_step / 1e3)
+    print("[bench] %.3f ms/step  ingest %.3f  finalize %.3f  segment %.3f ms  tile %s  host submit %.3f ms/step" %
+          (ms_step, phase[0], phase[1], phase[2], tile, 1e3 * float(np.median(host_submit))), file=sys.stderr,
+          flush=True)
+    if args.profile_pass:
+        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step}))
+        return
+
+    # roofline of the ingest kernel: algorithmic bytes per launch / measured launch time
+    per_launch_ms = phase[0] / n_launch
+    per_chunk = q.get(timeout=600)
+    proc.join(timeout=60)
+    n_pix = 0
+    U = 0
+    for (kept, u), (_, _, _, n) in zip(per_chunk, chunks):
+        n_pix += n * p.width * p.height
+        U += u
+    alg_bytes = n_pix * 1 + F * 36 + 12 * U
+    achieved = alg_bytes / n_launch / (per_launch_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(ingest_source_hash())
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "ingest_kernel (PNN scatter, 64 frames per launch)",
+            "alg_bytes_per_launch": int(alg_bytes / n_launch), "launch_ms": round(per_launch_ms, 5),
+            "distinct_voxels_per_launch": int(U / n_launch)}
+
+    extras = {}
+    if not args.no_extras:
+        try:
+            fps, ms = bench_splat(torch, usv, max(3, min(args.steps, 10)))
+            extras["fwd_bwd_frames_per_s"] = round(fps, 1)
+            extras["fwd_bwd_ms_per_step"] = round(ms, 3)
+        except Exception as e:  # report, do not hide
+            extras["fwd_bwd_error"] = repr(e)
+        try:
+            fps, ms, tot = bench_batched(torch, usv, max(2, min(args.steps, 5)))
+            extras["batched_frames_per_s"] = round(fps, 1)
+            extras["batched_ms_per_pass"] = round(ms, 3)
+            extras["batched_frames"] = tot
+        except Exception as e:
+            extras["batched_error"] = repr(e)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on the same step", file=sys.stderr, flush=True)
+        t_cpu = time_oracle_step(d, SEG)
+        cpu = {"value": round(F / t_cpu, 2), "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": "the full step (3600 frames in 57 calls + finalize + ALG2 segment/projection), "
+                         "single thread, %s" % cpu_model(),
+               "seconds": round(t_cpu, 2), "host_nproc": os.cpu_count()}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "frames/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "whole-spine sweep: 3600 frames 480x640 uint8 (0.1 mm px), 560 mm path with "
+                                  "+-20 mm meander and +-5 deg jitter, grid 400x240x1120 @ 0.5 mm, calls of 64 "
+                                  "frames, full finalize, ALG2 depth + slab projection h=2/5/10",
+                      "tile": list(tile), "parallelism": "single GPU"},
+           "breakdown_ms": {"ingest": round(phase[0], 4), "finalize": round(phase[1], 4),
+                            "segment_project": round(phase[2], 4)},
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extras)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,24 +1,35 @@
 // Pixel-nearest-neighbour compounding kernels for gfx950 (Sec. II.C: PNN distribution,
 // applied incrementally to newly acquired frames).
 //
-// One block (4 waves) compounds one tile of one frame.  Exactness of the tile's voxel
-// window: q_r(u, v) = fl(fl(M0 u) + fl(fl(M1 v) + M2)) is monotone in u and in v
-// (IEEE rounding is monotone), so its extremes over a pixel rectangle are reached at
-// the corner chosen by the signs of M0 and M1; the floor of those extremes bounds
-// every voxel the tile can hit.  Pixels are merged in an LDS window (one packed
-// 32-bit word per voxel: count << 20 | sum, tile <= 4095 pixels) and the window is
-// flushed with coalesced 32-bit global atomics: one for the uint32 sum and, for the
-// uint16 count, one per pair of voxels sharing a 32-bit word (lanes are aligned so
-// that lane parity equals voxel-index parity).
+// Work unit: one tile (tw x th pixels) of one frame.  Blocks are persistent and walk
+// the (frame, tile row, tile column) list with a stride that is a multiple of the
+// tile-column count, so each block -- and, with the hardware's round-robin placement
+// of blocks on the 8 XCDs, each XCD's L2 -- keeps to one lateral stripe of the volume.
+//
+// Exactness of a tile's voxel window: q_r(u, v) = fl(fl(M0 u) + fl(fl(M1 v) + M2)) is
+// monotone in u and in v (IEEE rounding is monotone), so its extremes over a pixel
+// rectangle are reached at the corner chosen by the signs of M0 and M1, and the floors
+// of those extremes bound every voxel the tile can reach.
+//
+// Per tile: pixels are merged in an LDS window (one packed word per voxel: count <<
+// cshift | sum; cshift 20 for tiles of <= 4095 pixels, 19 for bigger tiles whose frames
+// put at most 2056 pixels in any voxel, which the host checks per frame), then the window is flushed with coalesced 32-bit global
+// atomics -- one for the uint32 sum and, for the uint16 counts, one per 32-bit word
+// holding two neighbouring voxels (paired through a DPP lane shift) -- and zeroed as it
+// is read, ready for the next tile.  Count atomics return the old word; the overflow
+// test on it is made after a batch of atomics is in flight.  The rows of the next tile
+// are loaded before the current window is flushed.
 #include "usv_internal.h"
 
 namespace usv {
 
 namespace {
 
+constexpr int kMaxKr = 8;   // rows per lane of any tiling
+
 struct Win {
-  int32_t lo0, lo1, lo2, wx, wy, wz, we;
-  bool inside;
+  int32_t lo0, lo1, lo2, wx, wy, wz, we, rows;
+  bool inside, direct;
 };
 
 __device__ __forceinline__ float qcoord(float m0, float m1, float m2, float u, float v) {
@@ -42,16 +53,228 @@ __device__ __forceinline__ bool axis_range(float m0, float m1, float m2, float u
   return true;
 }
 
-// Compound one tile.  m: the frame's FP32 map, rows (du, dv, const).
-template <bool kAligned>
-__device__ __forceinline__ void ingest_tile(const SweepDesc &d, const uint8_t *__restrict__ img, const float m[9],
-                                            int tr, int tc, uint32_t *win, float4 *ctab) {
+// n / d for any n < 2^32 given m = floor(2^32 / d) (2^32 - 1 for d = 1): the estimate
+// umulhi(n, m) is low by at most one.
+__device__ __forceinline__ uint32_t udiv_m(uint32_t n, uint32_t d, uint32_t m) {
+  uint32_t q = __umulhi(n, m);
+  if (n - q * d >= d) ++q;
+  return q;
+}
+
+// n / d for n, d < 2^13 via FP32, rd = rcp(d) (within 1 ulp): (n + 1/2) / d lies at
+// least 1 / (2d) from an integer and the product below is within (n / d) 2^-21 < 1 / (2d)
+// of it (n < 2^13).
+__device__ __forceinline__ uint32_t udiv_small_f(uint32_t n, float rd) {
+  return (uint32_t)(((float)n + 0.5f) * rd);
+}
+
+// Placement of this lane's pixels inside any tile of a tiling.
+struct LaneGeo {
+  int uoff, voff;   // first column, first row (relative to the tile)
+  bool active;
+};
+
+__device__ __forceinline__ LaneGeo lane_geo(const Tiling &t) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = (int)__umulhi((uint32_t)lane, t.lr_magic);
+  const int c4 = lane - g * t.lr;
+  LaneGeo lg;
+  lg.uoff = 4 * c4;
+  lg.voff = g * 4 * t.kr + wave * t.kr;
+  lg.active = g < t.rpw;
+  return lg;
+}
+
+// the rows of a full tile this lane works on (4-byte loads; frames 4-byte aligned)
+__device__ __forceinline__ void load_rows(const SweepDesc &d, const uint8_t *__restrict__ img, int tr, int tc,
+                                          const LaneGeo &lg, uint32_t px[kMaxKr]) {
+  const uint8_t *base = img + (int64_t)(tr * d.t.th + lg.voff) * d.row_pitch + tc * d.t.tw + lg.uoff;
+#pragma unroll
+  for (int k = 0; k < kMaxKr; ++k)
+    px[k] = (lg.active && k < d.t.kr) ? *reinterpret_cast<const uint32_t *>(base + (int64_t)k * d.row_pitch) : 0u;
+}
+
+// Pixel phase.  kFast: full tile, window inside the grid, no mask, LDS window, rows
+// already loaded -- no per-pixel test at all.
+template <bool kAligned, bool kFast>
+__device__ __forceinline__ uint32_t pixel_phase(const SweepDesc &d, const uint8_t *__restrict__ img, const float m[9],
+                                                const Win &w, int cls, int u0, int u1, int v0, int v1,
+                                                const LaneGeo &lg, const uint32_t pre[kMaxKr], uint32_t *win,
+                                                const float4 *ctab) {
   const Tiling &t = d.t;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int u = u0 + lg.uoff;
+  uint32_t direct_kept = 0u;
+  if (!lg.active || u > u1) return 0u;
+  float a0[4], a1[4], a2[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float fu = (float)(u + j);
+    a0[j] = m[0] * fu;
+    a1[j] = m[3] * fu;
+    a2[j] = m[6] * fu;
+  }
+  const int vb = v0 + lg.voff;
+  const uint32_t wbase = (uint32_t)(w.lo0 + w.wx * (w.lo1 + w.wy * w.lo2));
+  const uint32_t wx = (uint32_t)w.wx, wy = (uint32_t)w.wy;
+  // window byte offset = 4 (iz wx wy + iy wx + ix - wbase)  (mod 2^32)
+  const uint32_t wx4 = 4u * wx, wxy4 = 4u * wx * wy, nb4 = 0u - 4u * wbase;
+  const uint32_t one = 1u << t.cshift;   // one pixel in the count field
+  if (kFast) {
+#pragma unroll
+    for (int k = 0; k < kMaxKr; ++k) {
+      if (k >= t.kr) break;
+      const float4 c = ctab[vb + k - v0];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t ix = (uint32_t)(a0[j] + c.x), iy = (uint32_t)(a1[j] + c.y), iz = (uint32_t)(a2[j] + c.z);
+        const uint32_t boff = __umul24(iy, wx4) + __umul24(iz, wxy4) + ((ix << 2) + nb4);
+        atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(win) + boff),
+                  one + ((pre[k] >> (8 * j)) & 0xFFu));
+      }
+    }
+    return 0u;
+  }
+  const uint32_t colmask = (u + 3 <= u1) ? 0xFu : ((1u << (u1 - u + 1)) - 1u);
+  const bool wide = colmask == 0xFu && kAligned;
+  uint32_t px[kMaxKr];
+#pragma unroll
+  for (int k = 0; k < kMaxKr; ++k) {
+    px[k] = 0u;
+    const int v = vb + k;
+    if (k < t.kr && v <= v1) {
+      const uint8_t *row = img + (int64_t)v * d.row_pitch;
+      if (wide) {
+        px[k] = *reinterpret_cast<const uint32_t *>(row + u);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (colmask & (1u << j)) px[k] |= (uint32_t)row[u + j] << (8 * j);
+      }
+    }
+  }
+  for (int k = 0; k < kMaxKr; ++k) {
+    const int v = vb + k;
+    if (k >= t.kr || v > v1) break;
+    uint32_t ok = colmask;
+    if (cls == 1) {
+      if (d.spans) {
+        const uint32_t sp = d.spans[v];
+        const uint32_t lo = sp & 0xFFFFu, span = (sp >> 16) - lo;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((uint32_t)(u + j) - lo >= span) ok &= ~(1u << j);
+      } else if (d.mask) {
+        const uint8_t *mr = d.mask + (int64_t)v * d.W;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((ok & (1u << j)) && mr[u + j] == 0) ok &= ~(1u << j);
+      }
+    }
+    const float4 c = ctab[v - v0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!(ok & (1u << j))) continue;
+      // c carries +0.0f in place of -0, so the unsigned compares equal 0 <= q < n (NaN fails)
+      const float qx = a0[j] + c.x, qy = a1[j] + c.y, qz = a2[j] + c.z;
+      if (!w.inside || w.direct) {
+        if (!((int)(__float_as_uint(qx) < d.nxb) & (int)(__float_as_uint(qy) < d.nyb) &
+              (int)(__float_as_uint(qz) < d.nzb)))
+          continue;
+      }
+      const uint32_t ix = (uint32_t)qx, iy = (uint32_t)qy, iz = (uint32_t)qz;
+      const uint32_t val = (px[k] >> (8 * j)) & 0xFFu;
+      if (!w.direct) {
+        const uint32_t boff = __umul24(iy, wx4) + __umul24(iz, wxy4) + ((ix << 2) + nb4);
+        atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(win) + boff), one | val);
+      } else {
+        const uint32_t gi = ix + (uint32_t)d.nx * (iy + (uint32_t)d.ny * iz);
+        atomicAdd(d.sum + gi, val);
+        atomicAdd(d.cnt32 + (gi >> 1), 1u << ((gi & 1u) * 16u));
+        ++direct_kept;
+      }
+    }
+  }
+  return direct_kept;
+}
+
+// Flush the window into the accumulators and zero it.  With an even grid width the
+// window is widened to even x-origin and width, so window entries 2p, 2p + 1 are the two
+// voxels of one 32-bit count word: one lane takes both (an 8-byte LDS read) and adds
+// the two sums with one 64-bit atomic and the two counts with one 32-bit atomic.  Odd grid widths take one entry per lane.  No atomic returns
+// a value: count overflow is detected afterwards from the kept-pixel total.  Returns the
+// number of pixels this lane flushed.
+template <bool kPairs, bool kZero>
+__device__ __forceinline__ uint32_t flush_window(const SweepDesc &d, const Win &w, uint32_t *win,
+                                                 const uint32_t *rowtab) {
+  const int tid = threadIdx.x;
+  const float rwx = __builtin_amdgcn_rcpf((float)w.wx);
+  const uint32_t cs = (uint32_t)d.t.cshift, smask = (1u << cs) - 1u;
+  uint32_t kept = 0u;
+  if (kPairs) {
+    const int npairs = w.we >> 1;
+    for (int p = tid; p < npairs; p += kBlock) {
+      const uint32_t e0 = 2u * (uint32_t)p;
+      const uint2 v = *reinterpret_cast<const uint2 *>(win + e0);
+      if (v.x | v.y) {
+        if (kZero) *reinterpret_cast<uint2 *>(win + e0) = make_uint2(0u, 0u);
+        const uint32_t row = udiv_small_f(e0, rwx);
+        const uint32_t gi = rowtab[row] + (e0 - row * (uint32_t)w.wx);
+        // both uint32 sums with one 64-bit add: a valid sum is <= 255 * 65535 < 2^32, so
+        // no carry crosses from the low word unless a count has already overflowed
+        atomicAdd(reinterpret_cast<unsigned long long *>(d.sum + gi),
+                  ((unsigned long long)(v.y & smask) << 32) | (unsigned long long)(v.x & smask));
+        const uint32_t c0 = v.x >> cs, c1 = v.y >> cs;
+        atomicAdd(d.cnt32 + (gi >> 1), c0 | (c1 << 16));
+        kept += c0 + c1;
+      }
+    }
+  } else {
+    for (int e = tid; e < w.we; e += kBlock) {
+      const uint32_t val = win[e];
+      if (val) {
+        if (kZero) win[e] = 0u;
+        const uint32_t row = udiv_small_f((uint32_t)e, rwx);
+        const uint32_t gi = rowtab[row] + ((uint32_t)e - row * (uint32_t)w.wx);
+        atomicAdd(d.sum + gi, val & smask);
+        atomicAdd(d.cnt32 + (gi >> 1), (val >> cs) << ((gi & 1u) * 16u));
+        kept += val >> cs;
+      }
+    }
+  }
+  return kept;
+}
+
+// add this wave's kept pixels to one of the kept counters
+__device__ __forceinline__ void add_kept(const SweepDesc &d, uint32_t kept) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o);
+  if ((threadIdx.x & 63) == 0 && kept)
+    atomicAdd(d.kept + ((blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) & (kKeptSlots - 1)),
+              (unsigned long long)kept);
+}
+
+// LDS of one tile.
+struct Smem {
+  uint32_t win[kWinMax];
+  float4 ctab[kMaxTileRows];
+  uint32_t rowtab[kMaxWinRows];
+};
+
+// Compound one tile (one block).  The lane's pixel rows of a full tile are loaded first,
+// so that they arrive while the window is set up.  Waves retire right after issuing
+// their flush atomics (no atomic returns a value), so no wave ever waits for them.
+template <bool kAligned>
+__device__ __forceinline__ void tile_once(const SweepDesc &d, const uint8_t *__restrict__ img, const float m[9],
+                                          int tr, int tc, Smem &sm) {
+  const Tiling &t = d.t;
+  const int tid = threadIdx.x;
   const int cls = d.tile_class ? d.tile_class[tr * t.tiles_x + tc] : 0;
   if (cls == 2) return;
   const int u0 = tc * t.tw, v0 = tr * t.th;
   const int u1 = min(u0 + t.tw, d.W) - 1, v1 = min(v0 + t.th, d.H) - 1;
+  const LaneGeo lg = lane_geo(t);
+  const bool full = kAligned && u0 + t.tw <= d.W && v0 + t.th <= d.H;
+  uint32_t px[kMaxKr] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  if (full) load_rows(d, img, tr, tc, lg, px);
 
   Win w;
   int hi0, hi1, hi2;
@@ -61,18 +284,32 @@ __device__ __forceinline__ void ingest_tile(const SweepDesc &d, const uint8_t *_
   if (!axis_range(m[3], m[4], m[5], fu0, fu1, fv0, fv1, d.ny, w.lo1, hi1, inside)) return;
   if (!axis_range(m[6], m[7], m[8], fu0, fu1, fv0, fv1, d.nz, w.lo2, hi2, inside)) return;
   w.inside = inside;
+  const bool pairs = (d.nx & 1) == 0;
+  if (pairs) {
+    // even x-origin and even width (stays inside the grid because nx is even)
+    w.lo0 &= ~1;
+    hi0 |= 1;
+  }
   w.wx = hi0 - w.lo0 + 1;
   w.wy = hi1 - w.lo1 + 1;
   w.wz = hi2 - w.lo2 + 1;
   const int64_t we64 = (int64_t)w.wx * w.wy * w.wz;
-  const bool direct = we64 > kWinMax;
-  w.we = direct ? 0 : (int32_t)we64;
+  const int64_t rows64 = (int64_t)w.wy * w.wz;
+  w.direct = we64 > kWinMax || rows64 > kMaxWinRows;
+  w.we = w.direct ? 0 : (int32_t)we64;
+  w.rows = w.direct ? 0 : (int32_t)rows64;
 
-  // zero the window; per-row constants c_r(v) (+0.0f turns -0 into +0 so that the
-  // unsigned compare below equals 0 <= q < n for every q, NaN included)
-  if (!direct) {
+  // zero the window; per-row constants c_r(v) (+0.0f turns -0 into +0 for the unsigned
+  // bound test); the global index of each window row's first voxel
+  if (!w.direct) {
     const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-    for (int e = tid * 4; e < w.we; e += kBlock * 4) *reinterpret_cast<uint4 *>(win + e) = z4;
+    for (int e = tid * 4; e < w.we; e += kBlock * 4) *reinterpret_cast<uint4 *>(sm.win + e) = z4;
+    const float rwy = __builtin_amdgcn_rcpf((float)w.wy);
+    for (int r = tid; r < w.rows; r += kBlock) {
+      const uint32_t ez = udiv_small_f((uint32_t)r, rwy);
+      const uint32_t ey = (uint32_t)r - ez * (uint32_t)w.wy;
+      sm.rowtab[r] = (uint32_t)w.lo0 + (uint32_t)d.nx * ((uint32_t)w.lo1 + ey + (uint32_t)d.ny * ((uint32_t)w.lo2 + ez));
+    }
   }
   if (tid < t.th) {
     const float fv = (float)(v0 + tid);
@@ -80,199 +317,131 @@ __device__ __forceinline__ void ingest_tile(const SweepDesc &d, const uint8_t *_
     c0 = c0 + m[2];
     c1 = c1 + m[5];
     c2 = c2 + m[8];
-    ctab[tid] = make_float4(c0 + 0.0f, c1 + 0.0f, c2 + 0.0f, 0.0f);
+    sm.ctab[tid] = make_float4(c0 + 0.0f, c1 + 0.0f, c2 + 0.0f, 0.0f);
   }
   __syncthreads();
 
-  const int g = (int)__umulhi((uint32_t)lane, t.lr_magic);
-  const int c4 = lane - g * t.lr;
-  const int u = u0 + 4 * c4;
-  if (g < t.rpw && u <= u1) {
-    float a0[4], a1[4], a2[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float fu = (float)(u + j);
-      a0[j] = m[0] * fu;
-      a1[j] = m[3] * fu;
-      a2[j] = m[6] * fu;
-    }
-    const uint32_t colmask = (u + 3 <= u1) ? 0xFu : ((1u << (u1 - u + 1)) - 1u);
-    const bool wide = colmask == 0xFu && kAligned;
-    const int vb = v0 + g * 4 * t.kr + wave * t.kr;
-    const uint32_t wbase = (uint32_t)(w.lo0 + w.wx * (w.lo1 + w.wy * w.lo2));
-    for (int k = 0; k < t.kr; ++k) {
-      const int v = vb + k;
-      if (v > v1) break;
-      const uint8_t *row = img + (int64_t)v * d.row_pitch;
-      uint32_t px;
-      if (wide) {
-        px = *reinterpret_cast<const uint32_t *>(row + u);
-      } else {
-        px = 0;
-        for (int j = 0; j < 4; ++j)
-          if (colmask & (1u << j)) px |= (uint32_t)row[u + j] << (8 * j);
-      }
-      uint32_t ok = colmask;
-      if (cls == 1) {
-        if (d.spans) {
-          const uint32_t sp = d.spans[v];
-          const uint32_t lo = sp & 0xFFFFu, span = (sp >> 16) - lo;
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if ((uint32_t)(u + j) - lo >= span) ok &= ~(1u << j);
-        } else if (d.mask) {
-          const uint8_t *mr = d.mask + (int64_t)v * d.W;
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if ((ok & (1u << j)) && mr[u + j] == 0) ok &= ~(1u << j);
-        }
-      }
-      const float4 c = ctab[v - v0];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (!(ok & (1u << j))) continue;
-        const float qx = a0[j] + c.x, qy = a1[j] + c.y, qz = a2[j] + c.z;
-        if (!w.inside || direct) {
-          if (!((int)(__float_as_uint(qx) < d.nxb) & (int)(__float_as_uint(qy) < d.nyb) & (int)(__float_as_uint(qz) < d.nzb)))
-            continue;
-        }
-        const uint32_t ix = (uint32_t)qx, iy = (uint32_t)qy, iz = (uint32_t)qz;
-        const uint32_t val = (px >> (8 * j)) & 0xFFu;
-        if (!direct) {
-          const uint32_t off = ix + (uint32_t)w.wx * (iy + (uint32_t)w.wy * iz);
-          atomicAdd(win + (off - wbase), (1u << 20) | val);
-        } else {
-          const uint32_t gi = ix + (uint32_t)d.nx * (iy + (uint32_t)d.ny * iz);
-          atomicAdd(d.sum + gi, val);
-          const uint32_t sh = (gi & 1u) * 16u;
-          const uint32_t old = atomicAdd(d.cnt32 + (gi >> 1), 1u << sh);
-          if (((old >> sh) & 0xFFFFu) == 0xFFFFu) d.err[0] = 1u;
-        }
-      }
-    }
+  uint32_t kept = 0u;
+  if (full && inside && !w.direct && cls == 0)
+    pixel_phase<kAligned, true>(d, img, m, w, cls, u0, u1, v0, v1, lg, px, sm.win, sm.ctab);
+  else
+    kept = pixel_phase<kAligned, false>(d, img, m, w, cls, u0, u1, v0, v1, lg, px, sm.win, sm.ctab);
+  if (!w.direct) {
+    __syncthreads();
+    if (pairs) kept += flush_window<true, false>(d, w, sm.win, sm.rowtab);
+    else kept += flush_window<false, false>(d, w, sm.win, sm.rowtab);
   }
-  __syncthreads();
-  if (direct) return;
+  add_kept(d, kept);
+}
 
-  // flush: 16-lane groups walk window rows (ey, ez) in x segments of 16 voxels
-  const int rows = w.wy * w.wz;
-  const int segs = (w.wx + 1 + 15) >> 4;
-  const int units = rows * segs;
-  const int xl = tid & 15;
-  // exact quotients n / d = umulhi(n, floor((2^32 - 1) / d) + 1) for 2 <= d, n < 2^13
-  const uint32_t mag_segs = 0xFFFFFFFFu / (uint32_t)segs + 1u;
-  const uint32_t mag_wy = 0xFFFFFFFFu / (uint32_t)w.wy + 1u;
-  for (int ui = tid >> 4; ui < units; ui += kBlock / 16) {
-    const int row = segs == 1 ? ui : (int)__umulhi((uint32_t)ui, mag_segs);
-    const int seg = ui - row * segs;
-    const int ez = w.wy == 1 ? row : (int)__umulhi((uint32_t)row, mag_wy);
-    const int ey = row - ez * w.wy;
-    const uint32_t rowbase = (uint32_t)d.nx * ((uint32_t)(w.lo1 + ey) + (uint32_t)d.ny * (uint32_t)(w.lo2 + ez));
-    const int gx = w.lo0 - (int)((w.lo0 + rowbase) & 1u) + seg * 16 + xl;
-    const int ex = gx - w.lo0;
-    const uint32_t val = (ex >= 0 && ex < w.wx) ? win[ex + w.wx * row] : 0u;
-    const uint32_t gi = rowbase + (uint32_t)gx;
-    if (val) atomicAdd(d.sum + gi, val & 0xFFFFFu);
-    const uint32_t c = val >> 20;
-    const uint32_t chi = __shfl_down(c, 1, 16);
-    if (!(xl & 1) && (c | chi)) {
-      const uint32_t old = atomicAdd(d.cnt32 + (gi >> 1), c | (chi << 16));
-      if ((old & 0xFFFFu) + c > 0xFFFFu || (old >> 16) + chi > 0xFFFFu) d.err[0] = 1u;
-    }
+// Launch over the frames of one call: block = (frame, tile row, tile column) with the
+// column fastest, so consecutive blocks (placed round-robin on the 8 XCDs) cover the
+// columns of one tile row.  kDevMaps: maps and frame indices in device memory.
+template <bool kAligned, bool kDevMaps>
+__device__ __forceinline__ void run_block(const SweepDesc &d, const float *__restrict__ Mdev,
+                                          const int32_t *__restrict__ fdev, const float (*Marg)[9],
+                                          const int32_t *farg, Smem &sm) {
+  const Tiling &t = d.t;
+  const uint32_t it = blockIdx.x;
+  const uint32_t per_frame = (uint32_t)(t.tiles_x * t.tiles_y);
+  const int f = (int)udiv_m(it, per_frame, t.pf_magic);
+  const int tile = (int)(it - (uint32_t)f * per_frame);
+  const int tr = (int)udiv_m((uint32_t)tile, (uint32_t)t.tiles_x, t.tx_magic);
+  const int tc = tile - tr * t.tiles_x;
+  float m[9];
+  int fi;
+  if (kDevMaps) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m[i] = Mdev[9 * f + i];
+    fi = fdev[f];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m[i] = Marg[f][i];
+    fi = farg[f];
   }
-  __syncthreads();
+  tile_once<kAligned>(d, d.frames + (int64_t)fi * d.frame_pitch, m, tr, tc, sm);
 }
 
 __global__ __launch_bounds__(kBlock) void ingest_kernel(IngestLaunch a) {
-  __shared__ __align__(16) uint32_t win[kWinMax];
-  __shared__ float4 ctab[kMaxTileRows];
-  const Tiling t = a.d.t;
-  const int b = blockIdx.x;
-  const int tc = b % t.tiles_x;
-  const int rest = b / t.tiles_x;
-  const int tr = rest % t.tiles_y;
-  const int f = rest / t.tiles_y;
-  float m[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) m[i] = a.M[f][i];
-  const uint8_t *img = a.d.frames + (int64_t)a.fidx[f] * a.d.frame_pitch;
-  ingest_tile<true>(a.d, img, m, tr, tc, win, ctab);
+  __shared__ __align__(16) Smem sm;
+  const SweepDesc d = a.d;
+  run_block<true, false>(d, nullptr, nullptr, a.M, a.fidx, sm);
 }
 
 __global__ __launch_bounds__(kBlock) void ingest_kernel_bytes(IngestLaunch a) {
-  __shared__ __align__(16) uint32_t win[kWinMax];
-  __shared__ float4 ctab[kMaxTileRows];
-  const Tiling t = a.d.t;
-  const int b = blockIdx.x;
-  const int tc = b % t.tiles_x;
-  const int rest = b / t.tiles_x;
-  const int tr = rest % t.tiles_y;
-  const int f = rest / t.tiles_y;
-  float m[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) m[i] = a.M[f][i];
-  const uint8_t *img = a.d.frames + (int64_t)a.fidx[f] * a.d.frame_pitch;
-  ingest_tile<false>(a.d, img, m, tr, tc, win, ctab);
+  __shared__ __align__(16) Smem sm;
+  const SweepDesc d = a.d;
+  run_block<false, false>(d, nullptr, nullptr, a.M, a.fidx, sm);
 }
 
-// The same tile kernel with the maps in device memory (used by captured graphs, whose
-// launch arguments are frozen at capture).
+// The same with the maps in device memory (used by captured graphs, whose launch
+// arguments are frozen at capture).
 __global__ __launch_bounds__(kBlock) void ingest_kernel_devm(SweepDesc d, const float *__restrict__ M,
                                                              const int32_t *__restrict__ fidx) {
-  __shared__ __align__(16) uint32_t win[kWinMax];
-  __shared__ float4 ctab[kMaxTileRows];
-  const int b = blockIdx.x;
-  const int tc = b % d.t.tiles_x;
-  const int rest = b / d.t.tiles_x;
-  const int tr = rest % d.t.tiles_y;
-  const int f = rest / d.t.tiles_y;
-  float m[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) m[i] = M[9 * f + i];
-  const uint8_t *img = d.frames + (int64_t)fidx[f] * d.frame_pitch;
+  __shared__ __align__(16) Smem sm;
   if (d.row_pitch % 4 == 0 && d.frame_pitch % 4 == 0 && (((uintptr_t)d.frames) & 3u) == 0)
-    ingest_tile<true>(d, img, m, tr, tc, win, ctab);
+    run_block<true, true>(d, M, fidx, nullptr, nullptr, sm);
   else
-    ingest_tile<false>(d, img, m, tr, tc, win, ctab);
+    run_block<false, true>(d, M, fidx, nullptr, nullptr, sm);
 }
 
-// Persistent batched ingest: blocks pull `items_per_pull` consecutive items of the flat
-// (sweep, frame, tile) list from a global counter until the list is exhausted; every
-// block reaches the exit test on each pull.
+// Batched ingest: one launch over the flat (sweep, frame, tile) list of every sweep;
+// block b finds its sweep by binary search over the sweeps' first items (each sweep's
+// list starts at a multiple of 8 items so that tile columns stay on one XCD).
 __global__ __launch_bounds__(kBlock) void ingest_batched_kernel(BatchLaunch a) {
-  __shared__ __align__(16) uint32_t win[kWinMax];
-  __shared__ float4 ctab[kMaxTileRows];
-  __shared__ int64_t pull_base;
-  for (;;) {
-    if (threadIdx.x == 0) pull_base = (int64_t)atomicAdd(a.counter, 1u) * a.items_per_pull;
-    __syncthreads();
-    const int64_t ib = pull_base;
-    __syncthreads();
-    if (ib >= a.n_items) break;
-    const int64_t ie = min(ib + (int64_t)a.items_per_pull, a.n_items);
-    for (int64_t it = ib; it < ie; ++it) {
-      int lo = 0, hi = a.n_sweeps - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.sweeps[mid].item_begin <= it) lo = mid; else hi = mid - 1;
-      }
-      const BatchSweep &s = a.sweeps[lo];
-      const int64_t local = it - s.item_begin;
-      const int f = (int)(local / s.items_per_frame);
-      const int tile = (int)(local - (int64_t)f * s.items_per_frame);
-      const int tr = tile / s.d.t.tiles_x;
-      const int tc = tile - tr * s.d.t.tiles_x;
-      float m[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) m[i] = s.M[(int64_t)f * 9 + i];
-      const uint8_t *img = s.d.frames + (int64_t)s.fidx[f] * s.d.frame_pitch;
-      const SweepDesc dd = s.d;
-      if (dd.row_pitch % 4 == 0 && dd.frame_pitch % 4 == 0 && (((uintptr_t)dd.frames) & 3u) == 0)
-        ingest_tile<true>(dd, img, m, tr, tc, win, ctab);
-      else
-        ingest_tile<false>(dd, img, m, tr, tc, win, ctab);
-    }
+  __shared__ __align__(16) Smem sm;
+  const int64_t it = blockIdx.x;
+  int lo = 0, hi = a.n_sweeps - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.sweeps[mid].item_begin <= it) lo = mid; else hi = mid - 1;
   }
+  const BatchSweep &s = a.sweeps[lo];
+  const uint32_t local = (uint32_t)(it - s.item_begin);
+  const SweepDesc d = s.d;
+  const uint32_t per_frame = (uint32_t)s.items_per_frame;
+  const int f = (int)udiv_m(local, per_frame, d.t.pf_magic);
+  if (f >= s.n_frames) return;   // padding item
+  const int tile = (int)(local - (uint32_t)f * per_frame);
+  const int tr = (int)udiv_m((uint32_t)tile, (uint32_t)d.t.tiles_x, d.t.tx_magic);
+  const int tc = tile - tr * d.t.tiles_x;
+  float m[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i] = s.M[(int64_t)f * 9 + i];
+  const uint8_t *img = d.frames + (int64_t)s.fidx[f] * d.frame_pitch;
+  if (d.row_pitch % 4 == 0 && d.frame_pitch % 4 == 0 && (((uintptr_t)d.frames) & 3u) == 0)
+    tile_once<true>(d, img, m, tr, tc, sm);
+  else
+    tile_once<false>(d, img, m, tr, tc, sm);
+}
+
+// Sum of the uint16 counts: per-block partials in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void count_sum_kernel(const uint32_t *__restrict__ cnt32, int64_t n,
+                                                        unsigned long long *__restrict__ partials) {
+  __shared__ unsigned long long red[4];
+  unsigned long long acc = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t w = cnt32[i];
+    acc += (w & 0xFFFFu) + (w >> 16);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void count_final_kernel(const unsigned long long *__restrict__ partials, int n_partials,
+                                   unsigned long long *__restrict__ kept, uint32_t *__restrict__ err, int store) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long stored = 0ull, added = 0ull;
+  for (int i = 0; i < n_partials; ++i) stored += partials[i];
+  if (store) {
+    kept[0] = stored;
+    for (int i = 1; i < kKeptSlots; ++i) kept[i] = 0ull;
+    return;
+  }
+  for (int i = 0; i < kKeptSlots; ++i) added += kept[i];
+  if (stored != added) err[0] = 1u;
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
@@ -287,23 +456,28 @@ __global__ void copy_u32_kernel(uint32_t *dst, const uint32_t *src, int64_t n) {
 
 }  // namespace
 
-hipError_t launch_ingest(const IngestLaunch &a, int n_blocks, hipStream_t s) {
+hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
   const bool aligned = (a.d.row_pitch % 4 == 0) && (a.d.frame_pitch % 4 == 0) &&
                        ((((uintptr_t)a.d.frames) & 3u) == 0);
   if (aligned)
-    hipLaunchKernelGGL(ingest_kernel, dim3(n_blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(ingest_kernel, dim3(n_items), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(ingest_kernel_bytes, dim3(n_blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(ingest_kernel_bytes, dim3(n_items), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t *fidx, int n_frames, hipStream_t s) {
-  hipLaunchKernelGGL(ingest_kernel_devm, dim3(n_frames * d.t.tiles_x * d.t.tiles_y), dim3(kBlock), 0, s, d, M, fidx);
+  const int n_items = n_frames * d.t.tiles_x * d.t.tiles_y;
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ingest_kernel_devm, dim3(n_items), dim3(kBlock), 0, s, d, M, fidx);
   return hipGetLastError();
 }
 
 hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(ingest_batched_kernel, dim3(n_blocks), dim3(kBlock), 0, s, a);
+  (void)n_blocks;
+  if (a.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ingest_batched_kernel, dim3((unsigned)a.n_items), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -312,6 +486,15 @@ hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_check(const uint32_t *cnt32, int64_t n_words, unsigned long long *kept,
+                              unsigned long long *partials, uint32_t *err, bool store, hipStream_t s) {
+  hipLaunchKernelGGL(count_sum_kernel, dim3(kCheckBlocks), dim3(256), 0, s, cnt32, n_words, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(count_final_kernel, dim3(1), dim3(64), 0, s, partials, kCheckBlocks, kept, err, store ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -38,7 +38,9 @@ struct ProbeState {
   uint32_t *d_spans = nullptr;
   uint8_t *d_mask = nullptr;
   uint8_t *d_tile_class = nullptr;
-  Tiling t{};
+  uint8_t *d_tile_class_safe = nullptr;
+  Tiling t{};        // tiling of ordinary frames
+  Tiling t_safe{};   // <= 4095-pixel tiling, for frames that put > 2056 pixels in one voxel
   double mask_density = 1.0;
 };
 
@@ -63,7 +65,8 @@ struct usv_volume {
   uint8_t *acc = nullptr;
   uint32_t *sum = nullptr;
   uint32_t *cnt32 = nullptr;
-  uint32_t *d_err = nullptr;     // [0] count overflow
+  uint32_t *d_err = nullptr;     // status block: [0] count overflow flag, then kept slots and partials
+  bool count_dirty = false;      // pixels added since the last count check
   int16_t *d_raw = nullptr;      // ALG2 raw depth scratch [nz][nx]
   std::vector<ProbeState> probes;
   usv_status sticky = USV_OK;
@@ -220,7 +223,8 @@ usv_box empty_box() {
 struct TileCand {
   int lr, kr;
 };
-const TileCand kCands[] = {{15, 4}, {16, 3}, {16, 2}, {8, 2}, {8, 1}, {16, 1}, {32, 1}, {12, 3}, {10, 2}};
+const TileCand kCands[] = {{15, 4}, {16, 3}, {16, 2}, {8, 2}, {8, 1}, {16, 1}, {32, 1}, {12, 3}, {10, 2},
+                           {15, 8}, {12, 6}, {16, 4}, {8, 4}, {32, 2}, {15, 6}};
 
 Tiling make_tiling(int lr, int kr, int W, int H) {
   Tiling t{};
@@ -232,6 +236,11 @@ Tiling make_tiling(int lr, int kr, int W, int H) {
   t.tiles_x = (W + t.tw - 1) / t.tw;
   t.tiles_y = (H + t.th - 1) / t.th;
   t.lr_magic = 0xFFFFFFFFu / (uint32_t)lr + 1u;
+  t.cshift = t.tw * t.th <= kSmallTilePixels ? 20 : 19;
+  t.tx_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)t.tiles_x);
+  t.pf_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)(t.tiles_x * t.tiles_y));
+  if (t.tiles_x == 1) t.tx_magic = 0xFFFFFFFFu;
+  if (t.tiles_x * t.tiles_y == 1) t.pf_magic = 0xFFFFFFFFu;
   return t;
 }
 
@@ -240,13 +249,15 @@ bool tiling_valid(const Tiling &t) {
 }
 
 // Heuristic default: largest tile whose planar footprint fits comfortably in the LDS
-// window, preferring a tile-column count that is a multiple of the 8 XCDs.
-Tiling default_tiling(const ProbeState &p, double voxel) {
+// window, preferring a tile-column count that is a multiple of the 8 XCDs.  small: only
+// tilings of <= 4095 pixels (always exact with the 20-bit sum field).
+Tiling default_tiling(const ProbeState &p, double voxel, bool small) {
   Tiling best{};
   double best_score = -1.0;
   for (const TileCand &c : kCands) {
     Tiling t = make_tiling(c.lr, c.kr, p.W, p.H);
     if (!tiling_valid(t)) continue;
+    if (small && t.cshift != 20) continue;
     const double ex = t.tw * p.sx / voxel + 2.0, ey = t.th * p.sy / voxel + 2.0;
     const double est = ex * ey * 3.0;
     if (est > 0.6 * kWinMax) continue;
@@ -263,13 +274,12 @@ Tiling default_tiling(const ProbeState &p, double voxel) {
   return best;
 }
 
-hipError_t upload_tile_class(ProbeState &p) {
-  if (p.d_tile_class) {
-    (void)hipFree(p.d_tile_class);
-    p.d_tile_class = nullptr;
+hipError_t upload_tile_class_for(const ProbeState &p, const Tiling &t, uint8_t *&dst) {
+  if (dst) {
+    (void)hipFree(dst);
+    dst = nullptr;
   }
   if (p.mask_kind == 0) return hipSuccess;
-  const Tiling &t = p.t;
   std::vector<uint8_t> cls((size_t)t.tiles_x * t.tiles_y);
   for (int ty = 0; ty < t.tiles_y; ++ty)
     for (int tx = 0; tx < t.tiles_x; ++tx) {
@@ -281,13 +291,19 @@ hipError_t upload_tile_class(ProbeState &p) {
         }
       cls[(size_t)ty * t.tiles_x + tx] = in == tot ? 0 : (in == 0 ? 2 : 1);
     }
-  hipError_t e = hipMalloc(&p.d_tile_class, cls.size());
+  hipError_t e = hipMalloc(&dst, cls.size());
   if (e != hipSuccess) return e;
-  return hipMemcpy(p.d_tile_class, cls.data(), cls.size(), hipMemcpyHostToDevice);
+  return hipMemcpy(dst, cls.data(), cls.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t upload_tile_class(ProbeState &p) {
+  hipError_t e = upload_tile_class_for(p, p.t, p.d_tile_class);
+  if (e != hipSuccess) return e;
+  return upload_tile_class_for(p, p.t_safe, p.d_tile_class_safe);
 }
 
 SweepDesc make_desc(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
-                    int64_t frame_pitch) {
+                    int64_t frame_pitch, bool safe = false) {
   SweepDesc d{};
   d.frames = frames;
   d.frame_pitch = frame_pitch;
@@ -295,9 +311,10 @@ SweepDesc make_desc(usv_volume *v, const ProbeState &p, const uint8_t *frames, i
   d.sum = v->sum;
   d.cnt32 = v->cnt32;
   d.err = v->d_err;
+  d.kept = reinterpret_cast<unsigned long long *>(reinterpret_cast<uint8_t *>(v->d_err) + 16);
   d.spans = p.mask_kind == 1 ? p.d_spans : nullptr;
   d.mask = p.mask_kind == 2 ? p.d_mask : nullptr;
-  d.tile_class = p.mask_kind ? p.d_tile_class : nullptr;
+  d.tile_class = p.mask_kind ? (safe ? p.d_tile_class_safe : p.d_tile_class) : nullptr;
   d.W = p.W;
   d.H = p.H;
   d.nx = v->nx;
@@ -307,15 +324,44 @@ SweepDesc make_desc(usv_volume *v, const ProbeState &p, const uint8_t *frames, i
   std::memcpy(&d.nxb, &fx, 4);
   std::memcpy(&d.nyb, &fy, 4);
   std::memcpy(&d.nzb, &fz, 4);
-  d.t = p.t;
+  d.t = safe ? p.t_safe : p.t;
   return d;
+}
+
+// Upper bound on the pixels of one frame that can land in one voxel.  Two pixels in one
+// voxel differ by d = (du, dv) with |G d|_inf < 1 + eps, G = the map's u and v columns
+// (3 x 2) and eps covering the FP32 rounding of both coordinate evaluations; hence
+// |d|_2 < sqrt(3)(1 + eps) / sigma_min(G), and the pixels all lie in one disc of that
+// radius around any of them: at most (2 floor(R) + 1)^2 of them.  sigma_min^2 is the
+// small eigenvalue of G^T G, taken as det / lambda_max with det = |a x b|^2 (no
+// cancellation for nearly parallel columns).
+double max_pixels_per_voxel(const float M[9], int W, int H) {
+  const double a[3] = {M[0], M[3], M[6]}, b[3] = {M[1], M[4], M[7]};
+  double mag = 0.0;
+  for (int r = 0; r < 3; ++r)
+    mag = std::max(mag, std::fabs(a[r]) * W + std::fabs(b[r]) * H + std::fabs((double)M[3 * r + 2]));
+  const double eps = 2.0 * 4.0 * mag * std::ldexp(1.0, -24);   // 4 roundings per coordinate, 2 pixels
+  const double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2], bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  const double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+  const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+  const double det = cx * cx + cy * cy + cz * cz;
+  const double lmax = 0.5 * (aa + bb + std::sqrt((aa - bb) * (aa - bb) + 4.0 * ab * ab));
+  if (!(lmax > 0.0) || !(det > 0.0) || !(eps < 0.01)) return 1e30;
+  const double lmin = 0.99 * det / lmax;
+  const double R = std::sqrt(3.0) * (1.0 + eps) / std::sqrt(lmin);
+  if (!(R < 1e4)) return 1e30;
+  const double side = 2.0 * std::floor(R) + 1.0;
+  return side * side;
 }
 
 // Fold + classify + dirty box for n poses.  Fills maps/fidx of the kept frames.
 usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *poses, int32_t n, std::vector<float> &maps,
-                          std::vector<int32_t> &fidx, usv_box *box) {
+                          std::vector<int32_t> &fidx, usv_box *box, std::vector<float> *smaps = nullptr,
+                          std::vector<int32_t> *sfidx = nullptr) {
   maps.clear();
   fidx.clear();
+  if (smaps) smaps->clear();
+  if (sfidx) sfidx->clear();
   usv_box b = empty_box();
   const int dims[3] = {v->nx, v->ny, v->nz};
   for (int32_t i = 0; i < n; ++i) {
@@ -327,19 +373,26 @@ usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *pose
     int lo[3], hi[3];
     if (!frame_box(M, p.W, p.H, dims, lo, hi)) continue;   // no pixel can land in the grid
     box_union(b, lo, hi);
-    maps.insert(maps.end(), M, M + 9);
-    fidx.push_back(i);
+    if (p.t.cshift != 20 && max_pixels_per_voxel(M, p.W, p.H) > kBigTileMaxPerVoxel) {
+      if (!smaps) return fail(v, USV_E_STATE, "frame needs the small-tile tiling");
+      smaps->insert(smaps->end(), M, M + 9);
+      sfidx->push_back(i);
+    } else {
+      maps.insert(maps.end(), M, M + 9);
+      fidx.push_back(i);
+    }
   }
   if (box) *box = b;
   return USV_OK;
 }
 
 usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
-                         int64_t frame_pitch, const std::vector<float> &maps, const std::vector<int32_t> &fidx) {
+                         int64_t frame_pitch, const std::vector<float> &maps, const std::vector<int32_t> &fidx,
+                         bool safe = false) {
   const int nk = (int)fidx.size();
   IngestLaunch a{};
-  a.d = make_desc(v, p, frames, row_pitch, frame_pitch);
-  const int per_frame = p.t.tiles_x * p.t.tiles_y;
+  a.d = make_desc(v, p, frames, row_pitch, frame_pitch, safe);
+  const int per_frame = a.d.t.tiles_x * a.d.t.tiles_y;
   for (int f0 = 0; f0 < nk; f0 += kLaunchFrames) {
     const int cnt = std::min(kLaunchFrames, nk - f0);
     a.n_frames = cnt;
@@ -387,7 +440,8 @@ usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *s
   v->acc = (uint8_t *)accum_dev;
   v->sum = (uint32_t *)accum_dev;
   v->cnt32 = (uint32_t *)((uint8_t *)accum_dev + 4 * v->nvox);
-  if (hipMalloc(&v->d_err, 16) != hipSuccess || hipMalloc(&v->d_raw, sizeof(int16_t) * (size_t)v->nx * v->nz) != hipSuccess) {
+  if (hipMalloc(&v->d_err, kStatusBytes) != hipSuccess ||
+      hipMalloc(&v->d_raw, sizeof(int16_t) * (size_t)v->nx * v->nz) != hipSuccess) {
     usv_destroy_volume(v);
     return USV_E_OOM;
   }
@@ -406,8 +460,29 @@ usv_status usv_reset(usv_volume *v) {
   const int64_t words = (int64_t)(usv_accumulator_bytes_of(v) / 4);
   usv_status st = check_hip(v, launch_zero_u32((uint32_t *)v->acc, words, v->stream), "zero accumulators");
   if (st != USV_OK) return st;
-  return check_hip(v, launch_zero_u32(v->d_err, 4, v->stream), "zero status");
+  v->count_dirty = false;
+  return check_hip(v, launch_zero_u32(v->d_err, (int64_t)(kStatusBytes / 4), v->stream), "zero status");
 }
+
+}  // extern "C"
+
+namespace {
+
+// Compare the sum of the stored uint16 counts with the pixels added (kept slots): any
+// wrapped count makes the stored sum smaller.  store: reset the slots to the stored sum.
+usv_status count_check(usv_volume *v, bool store) {
+  uint8_t *st = reinterpret_cast<uint8_t *>(v->d_err);
+  const int64_t words = (v->nvox + 1) / 2;
+  return check_hip(v,
+                   launch_count_check(v->cnt32, words, reinterpret_cast<unsigned long long *>(st + 16),
+                                      reinterpret_cast<unsigned long long *>(st + 16 + 8 * kKeptSlots), v->d_err,
+                                      store, v->stream),
+                   "count check");
+}
+
+}  // namespace
+
+extern "C" {
 
 usv_status usv_add_probe(usv_volume *v, const usv_probe_desc *pd, int32_t *probe_id) {
   if (!v || !probe_ok(pd) || !probe_id) return fail(v, USV_E_ARG, "invalid probe description");
@@ -454,7 +529,8 @@ usv_status usv_add_probe(usv_volume *v, const usv_probe_desc *pd, int32_t *probe
       }
     }
   }
-  p.t = default_tiling(p, v->s);
+  p.t = default_tiling(p, v->s, false);
+  p.t_safe = default_tiling(p, v->s, true);
   usv_status st = check_hip(v, upload_tile_class(p), "tile classes");
   if (st != USV_OK) return st;
   v->probes.push_back(std::move(p));
@@ -464,6 +540,11 @@ usv_status usv_add_probe(usv_volume *v, const usv_probe_desc *pd, int32_t *probe
 
 usv_status usv_sync(usv_volume *v) {
   if (!v) return USV_E_ARG;
+  if (v->count_dirty && v->sticky == USV_OK) {
+    usv_status cs = count_check(v, false);
+    if (cs != USV_OK) return cs;
+    v->count_dirty = false;
+  }
   usv_status st = check_hip(v, hipStreamSynchronize(v->stream), "stream synchronize");
   if (st != USV_OK) return st;
   uint32_t err[4];
@@ -484,8 +565,11 @@ usv_status usv_export_accumulators(usv_volume *v, void *dst) {
 
 usv_status usv_import_accumulators(usv_volume *v, const void *src) {
   if (!v || !src || (((uintptr_t)src) & 3u)) return fail(v, USV_E_ARG, "bad source");
-  return check_hip(v, launch_copy_u32((uint32_t *)v->acc, (const uint32_t *)src,
-                                      (int64_t)(usv_accumulator_bytes_of(v) / 4), v->stream), "import");
+  usv_status st = check_hip(v, launch_copy_u32((uint32_t *)v->acc, (const uint32_t *)src,
+                                               (int64_t)(usv_accumulator_bytes_of(v) / 4), v->stream), "import");
+  if (st != USV_OK) return st;
+  v->count_dirty = false;
+  return count_check(v, true);   // the imported counts become the pixels added so far
 }
 
 usv_status usv_destroy_volume(usv_volume *v) {
@@ -495,6 +579,7 @@ usv_status usv_destroy_volume(usv_volume *v) {
     if (p.d_spans) (void)hipFree(p.d_spans);
     if (p.d_mask) (void)hipFree(p.d_mask);
     if (p.d_tile_class) (void)hipFree(p.d_tile_class);
+    if (p.d_tile_class_safe) (void)hipFree(p.d_tile_class_safe);
   }
   if (v->d_err) (void)hipFree(v->d_err);
   if (v->d_raw) (void)hipFree(v->d_raw);
@@ -519,14 +604,17 @@ usv_status usv_ingest_frames(usv_volume *v, int32_t probe_id, const uint8_t *fra
     return fail(v, USV_E_ARG, "pitch smaller than the image");
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   if (n == 0) return USV_OK;
-  std::vector<float> maps;
-  std::vector<int32_t> fidx;
-  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, dirty_out);
+  std::vector<float> maps, smaps;
+  std::vector<int32_t> fidx, sfidx;
+  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, dirty_out, &smaps, &sfidx);
   if (st != USV_OK) {
     if (dirty_out) *dirty_out = empty_box();
     return st;
   }
-  return launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx);
+  v->count_dirty = true;
+  st = launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx);
+  if (st != USV_OK || sfidx.empty()) return st;
+  return launch_frames(v, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
 }
 
 usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, uint8_t *state) {
@@ -718,8 +806,9 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
       n_sweeps > 4096 || !vols[0])
     return USV_E_ARG;
   usv_volume *owner = vols[0];
-  std::vector<std::vector<float>> maps((size_t)n_sweeps);
-  std::vector<std::vector<int32_t>> fidx((size_t)n_sweeps);
+  // entry 2i: ordinary frames of sweep i; 2i+1: frames that need the small-tile tiling
+  std::vector<std::vector<float>> maps((size_t)n_sweeps * 2);
+  std::vector<std::vector<int32_t>> fidx((size_t)n_sweeps * 2);
   for (int32_t i = 0; i < n_sweeps; ++i) {
     usv_volume *v = vols[i];
     if (dirty_out) dirty_out[i] = empty_box();
@@ -736,8 +825,9 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
   for (int32_t i = 0; i < n_sweeps; ++i) {
     if (n_frames[i] == 0) continue;
     usv_volume *v = vols[i];
-    usv_status st = prepare_frames(v, v->probes[(size_t)probe_ids[i]], poses[i], n_frames[i], maps[(size_t)i],
-                                   fidx[(size_t)i], dirty_out ? &dirty_out[i] : nullptr);
+    const size_t e = 2 * (size_t)i;
+    usv_status st = prepare_frames(v, v->probes[(size_t)probe_ids[i]], poses[i], n_frames[i], maps[e], fidx[e],
+                                   dirty_out ? &dirty_out[i] : nullptr, &maps[e + 1], &fidx[e + 1]);
     if (st != USV_OK) {
       if (dirty_out)
         for (int32_t j = 0; j < n_sweeps; ++j) dirty_out[j] = empty_box();
@@ -746,7 +836,7 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
     }
   }
   // table layout: BatchSweep[n] | maps | fidx
-  size_t off_maps = align_up(sizeof(BatchSweep) * (size_t)n_sweeps, 256);
+  size_t off_maps = align_up(sizeof(BatchSweep) * (size_t)n_sweeps * 2, 256);
   size_t total_frames = 0;
   for (auto &f : fidx) total_frames += f.size();
   size_t off_fidx = align_up(off_maps + total_frames * 9 * sizeof(float), 256);
@@ -761,22 +851,25 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
   int64_t items = 0;
   size_t fpos = 0;
   int nsw = 0;
-  for (int32_t i = 0; i < n_sweeps; ++i) {
-    const size_t nf = fidx[(size_t)i].size();
+  for (size_t e = 0; e < fidx.size(); ++e) {
+    const size_t nf = fidx[e].size();
     if (nf == 0) continue;
+    const int32_t i = (int32_t)(e / 2);
     usv_volume *v = vols[i];
     const ProbeState &p = v->probes[(size_t)probe_ids[i]];
     BatchSweep b{};
-    b.d = make_desc(v, p, frames[i], row_pitch[i], frame_pitch[i]);
+    b.d = make_desc(v, p, frames[i], row_pitch[i], frame_pitch[i], (e & 1) != 0);
+    v->count_dirty = true;
     b.M = (const float *)(dbase + off_maps) + fpos * 9;
     b.fidx = (const int32_t *)(dbase + off_fidx) + fpos;
     b.n_frames = (int32_t)nf;
     b.item_begin = items;
-    b.items_per_frame = (int64_t)p.t.tiles_x * p.t.tiles_y;
-    std::memcpy(hm + fpos * 9, maps[(size_t)i].data(), nf * 9 * sizeof(float));
-    std::memcpy(hf + fpos, fidx[(size_t)i].data(), nf * sizeof(int32_t));
+    b.items_per_frame = (int64_t)b.d.t.tiles_x * b.d.t.tiles_y;
+    std::memcpy(hm + fpos * 9, maps[e].data(), nf * 9 * sizeof(float));
+    std::memcpy(hf + fpos, fidx[e].data(), nf * sizeof(int32_t));
     hs[nsw++] = b;
     items += b.items_per_frame * (int64_t)nf;
+    items = (items + 7) / 8 * 8;   // next sweep starts on a multiple of 8 items (XCD alignment)
     fpos += nf;
   }
   if (items == 0) return USV_OK;
@@ -794,17 +887,12 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
   if (st != USV_OK) return st;
   (void)hipEventRecord(owner->batch_stage.ev, s);
   owner->batch_stage.pending = true;
-  st = check_hip(owner, launch_zero_u32(owner->d_counter, 1, s), "counter reset");
-  if (st != USV_OK) return st;
   BatchLaunch a{};
   a.sweeps = (const BatchSweep *)owner->d_batch;
   a.n_sweeps = nsw;
   a.n_items = items;
-  a.items_per_pull = batch_items_per_pull();
-  a.counter = owner->d_counter;
-  const int64_t pulls = (items + a.items_per_pull - 1) / a.items_per_pull;
-  const int blocks = (int)std::min<int64_t>(pulls, (int64_t)device_cus() * 6);
-  st = check_hip(owner, launch_ingest_batched(a, blocks, s), "batched launch");
+  if (items > 0x7FFFFFFF) return fail(owner, USV_E_ARG, "batch too large for one launch");
+  st = check_hip(owner, launch_ingest_batched(a, (int)items, s), "batched launch");
   if (st != USV_OK) return st;
   for (int32_t i = 1; i < n_sweeps; ++i) {
     if (vols[i]->stream == s) continue;
@@ -846,18 +934,14 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
       }
     }
   }
-  std::vector<float> maps;
-  std::vector<int32_t> fidx;
-  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, nullptr);
-  if (st != USV_OK) return st;
-  st = usv_sync(v);
+  usv_status st = usv_sync(v);
   if (st == USV_E_DEVICE) return st;
   // scratch copy of the grid so that the volume's accumulators are not touched
   const size_t bytes = usv_accumulator_bytes_of(v);
   void *scratch = nullptr;
   uint32_t *err = nullptr;
   if (hipMalloc(&scratch, bytes) != hipSuccess) return fail(v, USV_E_OOM, "autotune scratch");
-  if (hipMalloc(&err, 16) != hipSuccess) {
+  if (hipMalloc(&err, kStatusBytes) != hipSuccess) {
     (void)hipFree(scratch);
     return fail(v, USV_E_OOM, "autotune scratch");
   }
@@ -883,13 +967,21 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
     if (!tiling_valid(t)) continue;
     p.t = t;
     if (upload_tile_class(p) != hipSuccess) continue;
+    // the frame split depends on the candidate's LDS packing
+    std::vector<float> maps, smaps;
+    std::vector<int32_t> fidx, sfidx;
+    if (prepare_frames(v, p, poses, n, maps, fidx, nullptr, &smaps, &sfidx) != USV_OK) break;
+    auto run = [&]() {
+      usv_status r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);
+      if (r == USV_OK && !sfidx.empty()) r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
+      return r;
+    };
     (void)launch_zero_u32((uint32_t *)scratch, (int64_t)(bytes / 4), v->stream);
-    usv_status s1 = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);   // warm-up
-    if (s1 != USV_OK) continue;
+    if (run() != USV_OK) continue;   // warm-up
     float ms_best = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
       (void)hipEventRecord(e0, v->stream);
-      (void)launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);
+      (void)run();
       (void)hipEventRecord(e1, v->stream);
       (void)hipEventSynchronize(e1);
       float ms = 0.0f;
@@ -940,7 +1032,8 @@ usv_status usv_graph_create(usv_volume *v, int32_t probe_id, usv_graph **out) {
     }
     std::memset(g->h_frame[k], 0, fb);
     std::memset(g->h_map[k], 0, 64);
-    SweepDesc d = make_desc(v, p, g->d_frame[k], p.W, (int64_t)fb);
+    // the pose is unknown at capture: use the small-tile tiling, exact for any pose
+    SweepDesc d = make_desc(v, p, g->d_frame[k], p.W, (int64_t)fb, true);
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       st = USV_E_DEVICE;
       break;
@@ -986,6 +1079,7 @@ usv_status usv_graph_launch(usv_graph *g, const uint8_t *frame_host, const doubl
   }
   std::memcpy(g->h_frame[k], frame_host, (size_t)p.W * p.H);
   std::memcpy(g->h_map[k], M, sizeof(M));
+  v->count_dirty = true;
   usv_status st = check_hip(v, hipGraphLaunch(g->exec[k], v->stream), "graph launch");
   if (st != USV_OK) return st;
   (void)hipEventRecord(g->done[k], v->stream);

@@ -9,16 +9,27 @@ namespace usv {
 // ---- nearest-voxel ingest --------------------------------------------------------------
 
 constexpr int kBlock = 256;          // threads per ingest block (4 waves of 64)
-constexpr int kWinMax = 6144;        // LDS voxel-window entries per block (24 KiB)
-constexpr int kMaxTileRows = 64;     // rows of a tile (per-row constant table)
-constexpr int kMaxTilePixels = 4095; // window entries pack (count << 20 | sum): count < 4096
+constexpr int kWinMax = 3584;        // LDS voxel-window entries per block (14 KiB: 8 blocks per CU)
+constexpr int kMaxWinRows = 256;     // window rows (y, z pairs) of one tile
+constexpr int kMaxTileRows = 128;    // rows of a tile (per-row constant table)
+constexpr int kMaxTilePixels = 8191; // window entries pack (count << cshift | sum)
+constexpr int kSmallTilePixels = 4095;   // tiles up to this size use cshift 20 with no condition
+constexpr double kBigTileMaxPerVoxel = 2056.0;   // 255 * 2056 < 2^19: big tiles (cshift 19) need
+                                                 // at most this many pixels of a frame per voxel
 constexpr int kLaunchFrames = 64;    // frames whose maps travel in one launch's arguments
+constexpr int kKeptSlots = 1024;     // kept-pixel counters (spread so that atomics do not collide)
+constexpr int kCheckBlocks = 1024;   // partial sums of the count check
+// device status block of a volume: flags | kept slots | check partials
+constexpr size_t kStatusBytes = 16 + 8 * kKeptSlots + 8 * kCheckBlocks;
 
 // Tiling of one probe's images: a tile is tw = 4*lr columns by th = 4*rpw*kr rows,
 // rpw = 64 / lr row groups per wave.
 struct Tiling {
   int32_t tw, th, lr, kr, rpw, tiles_x, tiles_y;
+  int32_t cshift;      // LDS window word = count << cshift | sum (20 for small tiles, 19 for big)
   uint32_t lr_magic;   // 2^32 / lr + 1: lane / lr == umulhi(lane, lr_magic) for lane < 64
+  uint32_t tx_magic;   // floor(2^32 / tiles_x): quotient estimate, corrected by one step
+  uint32_t pf_magic;   // floor(2^32 / (tiles_x * tiles_y)), likewise
 };
 
 // Everything one ingest job (one volume + one probe + its frames) needs on the device.
@@ -27,7 +38,8 @@ struct SweepDesc {
   int64_t frame_pitch, row_pitch;
   uint32_t *sum;           // uint32 [nvox]
   uint32_t *cnt32;         // uint16 [nvox] viewed as 32-bit words (2 voxels per word)
-  uint32_t *err;           // [0]: count overflow seen
+  uint32_t *err;           // [0]: count overflow seen (direct per-pixel path and the count check)
+  unsigned long long *kept;   // kKeptSlots counters of kept pixels (summed = pixels ever added)
   const uint32_t *spans;   // per row (lo | hi << 16) of a row-convex mask, or null
   const uint8_t *mask;     // general H*W mask, or null
   const uint8_t *tile_class;  // [tiles_y][tiles_x]: 0 inside mask, 1 partial, 2 outside; null = all 0
@@ -46,7 +58,7 @@ struct IngestLaunch {
   float M[kLaunchFrames][9];       // per frame: rows r = (du, dv, const)
 };
 
-// Batched persistent ingest: a flat list of (sweep, frame, tile) items.
+// Batched ingest: a flat list of (sweep, frame, tile) items in one launch.
 struct BatchSweep {
   SweepDesc d;
   const float *M;          // [n_frames][9] device
@@ -59,15 +71,19 @@ struct BatchSweep {
 struct BatchLaunch {
   const BatchSweep *sweeps;   // device array
   int32_t n_sweeps;
-  int64_t n_items;
-  int32_t items_per_pull;
-  uint32_t *counter;          // device work counter (zeroed before launch)
+  int64_t n_items;            // one block per item; each sweep starts at a multiple of 8
 };
 
-hipError_t launch_ingest(const IngestLaunch &a, int n_blocks, hipStream_t s);
+// n_items = frames x tiles, one block per item
+hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s);
 hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t s);
 hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t *fidx, int n_frames, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n_words, hipStream_t s);
+// Sum of all uint16 counts (cnt32 words) compared with the sum of the kept slots; a
+// difference means some count wrapped (overflow) and sets err[0].  With store = true the
+// kept slots are instead reset to that sum (after an import).
+hipError_t launch_count_check(const uint32_t *cnt32, int64_t n_words, unsigned long long *kept,
+                              unsigned long long *partials, uint32_t *err, bool store, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n_words, hipStream_t s);
 
 // ---- finalize ----------------------------------------------------------------------------

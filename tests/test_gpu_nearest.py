@@ -10,7 +10,9 @@ from gpu_util import add_probe, assert_accum_equal, gpu_volume, oracle_accum, sa
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(60, 64), (64, 48), (64, 32), (32, 64), (32, 32), (64, 16), (128, 8), (48, 60), (40, 48)]
+SHAPES = [(60, 64), (64, 48), (64, 32), (32, 64), (32, 32), (64, 16), (128, 8), (48, 60), (40, 48),
+          (128, 16), (60, 128), (48, 120), (64, 64), (32, 128), (60, 96)]
+BIG_SHAPES = [sh for sh in SHAPES if sh[0] * sh[1] > 4095]
 
 
 def run_gpu(case, chunks=None, order=None, tiling=None, frames_dev=None):
@@ -59,6 +61,25 @@ def test_every_tile_shape_bit_exact(shape):
     vol, _, _ = run_gpu(d, tiling=shape)
     vol.sync()
     assert_accum_equal(vol, oracle_accum(d), "tile %s" % (shape,))
+
+
+@pytest.mark.parametrize("shape", BIG_SHAPES)
+def test_dense_bright_pixels_on_big_tiles_bit_exact(shape):
+    # 0.01 mm pixels in 0.5 mm voxels: thousands of pixels of one frame share a voxel, so
+    # a big tile's 19-bit sum field could not hold them; such frames must go the
+    # small-tile way and still match the oracle bit for bit.
+    say("case: dense bright pixels, tile", shape)
+    case = synth.random_small_case(77, F=4, W=120, H=256, dims=(10, 10, 10), px=0.01, rot_deg=30.0)
+    case["frames"][:2] = 255
+    vol, _, _ = run_gpu(case, tiling=shape)
+    vol.sync()
+    assert_accum_equal(vol, oracle_accum(case), "dense %s" % (shape,))
+    # bright frames near the bound (about 2000 pixels per voxel allowed) stay on the big tile
+    case = synth.random_small_case(78, F=6, W=240, H=256, dims=(12, 12, 12), px=0.038, rot_deg=60.0)
+    case["frames"][:3] = 255
+    vol, _, _ = run_gpu(case, tiling=shape)
+    vol.sync()
+    assert_accum_equal(vol, oracle_accum(case), "near-bound %s" % (shape,))
 
 
 @pytest.mark.parametrize("seed", range(8))
