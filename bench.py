@@ -88,6 +88,51 @@ def traffic_from_profile(src_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
+def counters_summary(fetch_db, write_db, out_json):
+    """Summarise two rocprofv3 --pmc runs of `bench.py --profile-pass` (FETCH_SIZE, then
+    WRITE_SIZE; rocpd sqlite output) into HBM bytes per ingest launch.  Each counter is
+    scaled by what it reads for copy_u32_kernel, which the profile pass runs once on a
+    buffer of known size (the accumulator export), so the figure is in true bytes."""
+    import sqlite3
+    import synth
+    from paper_2412_00058_amd.usv import accumulator_bytes
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        agg = {}
+        for name, cname, val, disp in con.execute(
+                "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+            if cname != counter:
+                continue
+            k = name.replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
+            a = agg.setdefault(k, {})
+            a[disp] = a.get(disp, 0.0) + float(val)
+        return {k: (sum(v.values()) / len(v), len(v)) for k, v in agg.items()}
+
+    g = synth.cfg2(count=0)["grid"]
+    copy_bytes = accumulator_bytes(g.dims)
+    fetch = per_kernel(fetch_db, "FETCH_SIZE")
+    write = per_kernel(write_db, "WRITE_SIZE")
+    f_copy, w_copy = fetch["copy_u32_kernel"][0] * 1024.0, write["copy_u32_kernel"][0] * 1024.0
+    kf, kw = copy_bytes / f_copy, copy_bytes / w_copy
+    f_ing, n_f = fetch["ingest_kernel"]
+    w_ing, n_w = write["ingest_kernel"]
+    rec = {"ingest_source_sha256": ingest_source_hash(),
+           "fetch_kib_per_dispatch": round(f_ing, 1), "write_kib_per_dispatch": round(w_ing, 1),
+           "dispatches": [n_f, n_w], "copy_bytes": copy_bytes,
+           "copy_fetch_kib": round(f_copy / 1024.0, 1), "copy_write_kib": round(w_copy / 1024.0, 1),
+           "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
+           "hbm_bytes_per_launch": int(f_ing * 1024.0 * kf + w_ing * 1024.0 * kw)}
+    for k in sorted(set(fetch) | set(write)):
+        f = fetch.get(k, (0.0, 0))[0]
+        w = write.get(k, (0.0, 0))[0]
+        print("%-28s FETCH %12.1f KiB  WRITE %12.1f KiB  per dispatch (raw)" % (k, f, w))
+    print(json.dumps(rec, indent=1))
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+
+
 def ingest_source_hash():
     h = hashlib.sha256()
     for f in ("ingest.hip", "usv_internal.h"):
@@ -173,7 +218,14 @@ def main():
     ap.add_argument("--cache", default=None,
                     help="load the generated sweep from this .npz (written there if missing); lets a profiled "
                          "run skip the generator's worker processes")
+    ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None,
+                    help="no GPU: summarise two rocprofv3 --pmc result databases of the profile pass into "
+                         "profiles/ingest_cfg2_counters.json")
     args = ap.parse_args()
+    if args.counters_summary:
+        counters_summary(args.counters_summary[0], args.counters_summary[1],
+                         os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json"))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build is single-GPU only (see DESIGN.md, sharding plan)",
               file=sys.stderr)
@@ -278,7 +330,11 @@ def main():
           (ms_step, phase[0], phase[1], phase[2], tile, 1e3 * float(np.median(host_submit))), file=sys.stderr,
           flush=True)
     if args.profile_pass:
-        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step}))
+        # one plain copy of known size (the accumulator export) to calibrate byte counters
+        snap = vol.export_accumulators()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step,
+                          "copy_bytes": snap.numel() * snap.element_size()}))
         return
 
     # roofline of the ingest kernel: algorithmic bytes per launch / measured launch time
