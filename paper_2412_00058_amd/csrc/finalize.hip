@@ -1,19 +1,25 @@
 // Normalise + PNN hole fill for gfx950 (Sec. II.C: the second PNN stage fills voxels no
 // pixel reached from their measured neighbours).
 //
-// A block owns a 64 (x) by 4 (y) column of output voxels and marches along z.  Each
-// step loads one (66 x 6) plane with a one-voxel halo, normalises it into an LDS word
-// w = measured ? (V | 1 << 16) : 0, and forms the in-plane 3x3 sum of w for its voxel;
-// the 3x3x3 sum is the sum of three consecutive in-plane sums kept in registers.  The
-// sum of w over the 26 neighbours carries sum(V) in its low 16 bits (<= 26 * 255) and
-// the measured count above them.  Planes are double buffered: one barrier per plane.
+// A block owns a 64 (x) by 16 (y) column of output voxels and marches along z over a
+// chunk of planes.  Lane x of wave w owns rows 4w .. 4w + 3 of the column.  Each step
+// normalises one (66 x 18) plane with a one-voxel halo into LDS words
+// w = measured ? (V | 1 << 16) : 0, and every lane forms the in-plane 3x3 sums of w for
+// its four voxels (a 3-wide column sum over six rows, reused by the four outputs); the
+// 3x3x3 sum is the sum of three consecutive in-plane sums kept in registers.  The sum of
+// w over the 26 neighbours carries sum(V) in its low 16 bits (<= 26 * 255) and the
+// measured count above them.  Raw sums and counts of the next two planes are loaded
+// into registers ahead of use, so each lane keeps three planes of loads in flight;
+// LDS planes are double buffered, one barrier per plane.
 #include "usv_internal.h"
 
 namespace usv {
 
 namespace {
 
-constexpr int TX = 64, TY = 4, PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+constexpr int TX = 64, TY = 16, RPW = 4, PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+constexpr int kHalo = 2 * PY + 2 * TX;   // halo words of a plane: two columns, two rows
+constexpr int kDepth = 3;                // planes of raw loads in flight per lane
 
 // floor(num / den) for num < 2^26, 0 < den < 2^18: approximate quotient, corrected once.
 __device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t den) {
@@ -31,72 +37,136 @@ __device__ __forceinline__ uint32_t normalise(uint32_t s, uint32_t c) {
   return (q > 255u ? 255u : q) | (1u << 16);
 }
 
+// Raw accumulator words of one plane for this lane: its four own voxels and at most one
+// halo voxel (threads 0 .. kHalo - 1).
+struct Raw {
+  uint32_t s[RPW], c[RPW];
+  uint32_t hs, hc;
+};
+
 __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
   __shared__ uint32_t plane[2][PLANE];
-  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> 6;
-  const int x = a.lo[0] + blockIdx.x * TX + tx;
-  const int y = a.lo[1] + blockIdx.y * TY + ty;
+  const int tid = threadIdx.x;
+  const int tx = tid & (TX - 1), wv = tid >> 6;
+  const int x0 = a.lo[0] + blockIdx.x * TX, y0 = a.lo[1] + blockIdx.y * TY;
   const int zs = a.lo[2] + blockIdx.z * a.zchunk;
   const int ze = min(zs + a.zchunk, a.hi[2]);
-  const int xb = a.lo[0] + blockIdx.x * TX - 1, yb = a.lo[1] + blockIdx.y * TY - 1;
   const int64_t nxy = (int64_t)a.nx * a.ny;
+  const int x = x0 + tx;
+  const bool xin = x < a.nx;
+  // this lane's halo voxel (plane coordinates): left / right columns, then top / bottom rows
+  int hpx = -1, hpy = -1;
+  if (tid < 2 * PY) {
+    hpx = tid < PY ? 0 : PX - 1;
+    hpy = tid < PY ? tid : tid - PY;
+  } else if (tid < kHalo) {
+    const int e = tid - 2 * PY;
+    hpx = 1 + (e & (TX - 1));
+    hpy = e < TX ? 0 : PY - 1;
+  }
+  const int hx = x0 - 1 + hpx, hy = y0 - 1 + hpy;
+  const bool hin = hpx >= 0 && hx >= 0 && hx < a.nx && hy >= 0 && hy < a.ny;
+  const int64_t hoff = (int64_t)hx + (int64_t)a.nx * hy;
 
-  auto load = [&](int slot, int z) {
-    for (int e = threadIdx.x; e < PLANE; e += 256) {
-      const int py = e / PX, px = e - py * PX;
-      const int gx = xb + px, gy = yb + py;
-      uint32_t w = 0;
-      if (z >= 0 && z < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) {
-        const int64_t i = (int64_t)gx + (int64_t)a.nx * gy + nxy * z;
-        w = normalise(a.sum[i], a.cnt[i]);
+  auto load = [&](int z, Raw &r) {
+    const bool zin = z >= 0 && z < a.nz;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int y = y0 + wv * RPW + k;
+      r.s[k] = 0u;
+      r.c[k] = 0u;
+      if (zin && xin && y < a.ny) {
+        const int64_t i = (int64_t)x + (int64_t)a.nx * y + nxy * z;
+        r.s[k] = a.sum[i];
+        r.c[k] = a.cnt[i];
       }
-      plane[slot][e] = w;
+    }
+    r.hs = 0u;
+    r.hc = 0u;
+    if (zin && hin) {
+      r.hs = a.sum[hoff + nxy * z];
+      r.hc = a.cnt[hoff + nxy * z];
     }
   };
-  auto psum = [&](int slot, uint32_t &centre) {
-    const uint32_t *p = plane[slot];
-    const int c = (ty + 1) * PX + tx + 1;
-    centre = p[c];
-    return p[c - PX - 1] + p[c - PX] + p[c - PX + 1] + p[c - 1] + p[c] + p[c + 1] + p[c + PX - 1] + p[c + PX] +
-           p[c + PX + 1];
+  auto store = [&](int slot, const Raw &r) {
+    uint32_t *p = plane[slot];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) p[(1 + wv * RPW + k) * PX + 1 + tx] = normalise(r.s[k], r.c[k]);
+    if (hpx >= 0) p[hpy * PX + hpx] = normalise(r.hs, r.hc);
+  };
+  // in-plane 3x3 sums of this lane's four voxels, and their centre words
+  auto psum = [&](int slot, uint32_t P[RPW], uint32_t C[RPW]) {
+    const uint32_t *p = plane[slot] + (wv * RPW) * PX + tx;
+    uint32_t col[RPW + 2];
+#pragma unroll
+    for (int r = 0; r < RPW + 2; ++r) {
+      const uint32_t a0 = p[r * PX], a1 = p[r * PX + 1], a2 = p[r * PX + 2];
+      col[r] = a0 + a1 + a2;
+      if (r >= 1 && r <= RPW) C[r - 1] = a1;
+    }
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) P[k] = col[k] + col[k + 1] + col[k + 2];
   };
 
-  uint32_t cm, c0, cp;
-  load((zs - 1) & 1, zs - 1);
+  Raw q[kDepth];
+  // planes zs - 1 and zs are normalised first; loads run kDepth planes ahead
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d) load(zs - 1 + d, q[d]);
+  uint32_t Pm[RPW], P0[RPW], Pp[RPW], Cm[RPW], C0[RPW], Cp[RPW];
+  store((zs - 1) & 1, q[0]);
+  load(zs - 1 + kDepth, q[0]);
   __syncthreads();
-  uint32_t Pm = psum((zs - 1) & 1, cm);
-  load(zs & 1, zs);
+  psum((zs - 1) & 1, Pm, Cm);
+  store(zs & 1, q[1]);
+  load(zs + kDepth, q[1]);
   __syncthreads();
-  uint32_t P0 = psum(zs & 1, c0);
-  const bool active = x < a.hi[0] && y < a.hi[1];
+  psum(zs & 1, P0, C0);
   const uint32_t fmin = (uint32_t)(a.fill_min < 1 ? 1 : a.fill_min);
-  for (int z = zs; z < ze; ++z) {
-    load((z + 1) & 1, z + 1);
+  // one plane: r holds the raw words of plane z + 1 and is refilled with plane z + 1 + kDepth
+  auto step = [&](int z, Raw &r) {
+    store((z + 1) & 1, r);
+    load(z + 1 + kDepth, r);
     __syncthreads();
-    const uint32_t Pp = psum((z + 1) & 1, cp);
-    if (active) {
-      const int64_t i = (int64_t)x + (int64_t)a.nx * y + nxy * z;
-      uint32_t V, st;
-      if (c0 >> 16) {
-        V = c0 & 0xFFu;
-        st = 1u;
-      } else {
-        const uint32_t nb = Pm + P0 + Pp;   // centre is 0 (not measured)
-        const uint32_t n = nb >> 16, sv = nb & 0xFFFFu;
-        if (n >= fmin) {
-          V = udiv_small(2u * sv + n, 2u * n);
-          st = 2u;
+    psum((z + 1) & 1, Pp, Cp);
+    if (xin && x < a.hi[0]) {
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        const int y = y0 + wv * RPW + k;
+        if (y >= a.hi[1]) continue;
+        const int64_t i = (int64_t)x + (int64_t)a.nx * y + nxy * z;
+        uint32_t V, st;
+        if (C0[k] >> 16) {
+          V = C0[k] & 0xFFu;
+          st = 1u;
         } else {
-          V = 0u;
-          st = 0u;
+          const uint32_t nb = Pm[k] + P0[k] + Pp[k];   // centre is 0 (not measured)
+          const uint32_t n = nb >> 16, sv = nb & 0xFFFFu;
+          if (n >= fmin) {
+            V = udiv_small(2u * sv + n, 2u * n);
+            st = 2u;
+          } else {
+            V = 0u;
+            st = 0u;
+          }
         }
+        a.V[i] = (uint8_t)V;
+        if (a.state) a.state[i] = (uint8_t)st;
       }
-      a.V[i] = (uint8_t)V;
-      if (a.state) a.state[i] = (uint8_t)st;
     }
-    Pm = P0;
-    P0 = Pp;
-    c0 = cp;
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      Pm[k] = P0[k];
+      P0[k] = Pp[k];
+      C0[k] = Cp[k];
+    }
+  };
+  // the register sets rotate q[2], q[0], q[1] (static indices: no scratch)
+  for (int z = zs; z < ze; z += kDepth) {
+    step(z, q[2]);
+    if (z + 1 >= ze) break;
+    step(z + 1, q[0]);
+    if (z + 2 >= ze) break;
+    step(z + 2, q[1]);
   }
 }
 
@@ -106,6 +176,7 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
   const int ex = a.hi[0] - a.lo[0], ey = a.hi[1] - a.lo[1], ez = a.hi[2] - a.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
   dim3 grid((ex + TX - 1) / TX, (ey + TY - 1) / TY, (ez + a.zchunk - 1) / a.zchunk);
+  static_assert(kHalo <= 256, "one halo word per thread");
   hipLaunchKernelGGL(finalize_kernel, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }

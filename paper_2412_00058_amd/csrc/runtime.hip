@@ -642,7 +642,7 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
       a.hi[k] = dims[k];
     }
   }
-  a.zchunk = 16;
+  a.zchunk = 32;
   return check_hip(v, launch_finalize(a, v->stream), "finalize launch");
 }
 

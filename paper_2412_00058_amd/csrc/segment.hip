@@ -12,39 +12,88 @@ namespace usv {
 
 namespace {
 
+// Table II Step 2 on one column: lane = (x, y segment).  The scan range [y_lo, ymax] is
+// split into four segments, one per wave of the block; each lane scans its segment
+// downward (loads issued eight rows at a time) keeping the first maximum, i.e. the
+// deepest, and the four segment winners are combined with ties to the deeper segment.
+constexpr int kSeg = 4, kUnroll = 8;
+
 __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
-  const int x = blockIdx.x * 256 + threadIdx.x;
+  __shared__ int32_t best_s_sh[kSeg][64], best_y_sh[kSeg][64];
+  const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int x = blockIdx.x * 64 + lane;
   const int z = blockIdx.y;
-  if (x >= a.nx) return;
   const int64_t nxy = (int64_t)a.nx * a.ny;
-  const uint8_t *col = a.V + (int64_t)z * nxy + x;
   const int ymax = a.ny - 1 - a.k;
-  int best = -1;
-  int best_s = 0;
-  if (ymax >= a.y_lo) {
-    int below = 0;   // sum of V(y+1 .. y+k)
-    for (int j = 1; j <= a.k; ++j) below += col[(int64_t)(ymax + j) * a.nx];
-    const int thr = a.k * a.tau_G;
-    for (int y = ymax; y >= a.y_lo; --y) {   // descending: first maximum found is the deepest
-      const int here = col[(int64_t)y * a.nx];
-      const int sc = a.k * here - below;
-      if (here >= a.tau_I && sc >= thr && (best < 0 || sc > best_s)) {
-        best = y;
-        best_s = sc;
+  int best = -1, best_s = 0;
+  if (x < a.nx && ymax >= a.y_lo) {
+    const uint8_t *col = a.V + (int64_t)z * nxy + x;
+    const int len = ymax - a.y_lo + 1;
+    const int per = (len + kSeg - 1) / kSeg;
+    const int yhi = ymax - seg * per;                  // this segment: y in [ylo, yhi]
+    const int ylo = max(a.y_lo, yhi - per + 1);
+    if (yhi >= ylo) {
+      int below = 0;   // sum of V(y+1 .. y+k) for y = yhi
+      for (int j = 1; j <= a.k; ++j) below += col[(int64_t)(yhi + j) * a.nx];
+      const int thr = a.k * a.tau_G;
+      for (int yb = yhi; yb >= ylo; yb -= kUnroll) {
+        int here[kUnroll], leave[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int y = yb - u;
+          here[u] = y >= ylo ? col[(int64_t)y * a.nx] : 0;
+          leave[u] = y >= ylo ? col[(int64_t)(y + a.k) * a.nx] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int y = yb - u;
+          if (y < ylo) break;
+          const int sc = a.k * here[u] - below;
+          if (here[u] >= a.tau_I && sc >= thr && (best < 0 || sc > best_s)) {
+            best = y;
+            best_s = sc;
+          }
+          below += here[u] - leave[u];
+        }
       }
-      below += here - col[(int64_t)(y + a.k) * a.nx];
     }
   }
-  a.raw[(int64_t)z * a.nx + x] = (int16_t)best;
+  best_s_sh[seg][lane] = best_s;
+  best_y_sh[seg][lane] = best;
+  __syncthreads();
+  if (seg == 0 && x < a.nx) {
+    // segment 0 is the deepest; a later (shallower) segment wins only with a larger score
+    int by = best_y_sh[0][lane], bs = best_s_sh[0][lane];
+    for (int g = 1; g < kSeg; ++g) {
+      const int y = best_y_sh[g][lane], sc = best_s_sh[g][lane];
+      if (y >= 0 && (by < 0 || sc > bs)) {
+        by = y;
+        bs = sc;
+      }
+    }
+    a.raw[(int64_t)z * a.nx + x] = (int16_t)by;
+  }
 }
 
 constexpr int SX = 64, SZ = 4, RMAX = 8;
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
 
 __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
   __shared__ int16_t tile[(SZ + 2 * RMAX) * (SX + 2 * RMAX)];
   const int tx = threadIdx.x & (SX - 1), tz = threadIdx.x >> 6;
   const int x = blockIdx.x * SX + tx, z = blockIdx.y * SZ + tz;
-  int d;
+  const bool active = x < a.nx && z < a.nz;
+  int d = 0;
   if (a.mode == 0) {
     const int r = a.r, pw = SX + 2 * r, ph = SZ + 2 * r;
     const int xb = blockIdx.x * SX - r, zb = blockIdx.y * SZ - r;
@@ -54,8 +103,8 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
       tile[e] = (gx >= 0 && gx < a.nx && gz >= 0 && gz < a.nz) ? a.raw[(int64_t)gz * a.nx + gx] : (int16_t)-1;
     }
     __syncthreads();
-    if (x >= a.nx || z >= a.nz) return;
-    // lower median: the valid value whose rank interval [less, less + equal) holds (n-1)/2
+    // lower median of the valid depths: the smallest v with #{w <= v} > (n - 1) / 2,
+    // found by bisection over [0, ny) (depths are column indices)
     int n = 0;
     for (int dz = 0; dz <= 2 * r; ++dz)
       for (int dx = 0; dx <= 2 * r; ++dx) n += tile[(tz + dz) * pw + tx + dx] >= 0;
@@ -63,26 +112,21 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
       d = a.fallback_y;
     } else {
       const int want = (n - 1) >> 1;
-      d = a.fallback_y;
-      for (int i = 0; i <= 2 * r; ++i)
-        for (int j = 0; j <= 2 * r; ++j) {
-          const int v = tile[(tz + i) * pw + tx + j];
-          if (v < 0) continue;
-          int less = 0, eq = 0;
-          for (int dz = 0; dz <= 2 * r; ++dz)
-            for (int dx = 0; dx <= 2 * r; ++dx) {
-              const int w = tile[(tz + dz) * pw + tx + dx];
-              less += (w >= 0) & (w < v);
-              eq += w == v;
-            }
-          if (less <= want && want < less + eq) {
-            d = v;
-            i = j = 2 * r + 1;   // done
+      int lo = 0, hi = a.ny - 1;   // answer in [lo, hi]
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        int le = 0;
+        for (int dz = 0; dz <= 2 * r; ++dz)
+          for (int dx = 0; dx <= 2 * r; ++dx) {
+            const int w = tile[(tz + dz) * pw + tx + dx];
+            le += (w >= 0) & (w <= mid);
           }
-        }
+        if (le > want) hi = mid;
+        else lo = mid + 1;
+      }
+      d = lo;
     }
   } else {
-    if (x >= a.nx || z >= a.nz) return;
     double cut;
     if (a.mode == 1) {
       const double zc = a.origin_z + ((double)z + 0.5) * a.s;
@@ -96,26 +140,42 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
   }
   const int64_t plane = (int64_t)a.nx * a.nz;
   const int64_t o = (int64_t)z * a.nx + x;
-  a.depth[o] = (int16_t)d;
+  if (active) a.depth[o] = (int16_t)d;
   int hmax = 0;
   for (int i = 0; i < a.n_half; ++i) hmax = max(hmax, a.half[i]);
   int S[4] = {0, 0, 0, 0}, C[4] = {0, 0, 0, 0}, Mx[4] = {0, 0, 0, 0};
-  const int y0 = max(0, d - hmax), y1 = min(a.ny - 1, d + hmax);
+  // the wave walks the union of its lanes' slabs row by row, so every load is one
+  // contiguous row segment of the wave's 64 columns
+  const int ya = active ? max(0, d - hmax) : 0x7FFFFFFF;
+  const int yz = active ? min(a.ny - 1, d + hmax) : -1;
+  const int y0 = wave_min(ya), y1 = wave_max(yz);
   const int64_t nxy = (int64_t)a.nx * a.ny;
-  for (int y = y0; y <= y1; ++y) {
-    const int64_t i = (int64_t)z * nxy + (int64_t)y * a.nx + x;
-    if (a.state[i] == 0) continue;
-    const int v = a.V[i];
-    const int ady = y > d ? y - d : d - y;
+  const int64_t base = (int64_t)(active ? z : 0) * nxy + (active ? x : 0);
+  for (int yb = y0; yb <= y1; yb += kUnroll) {
+    int vv[kUnroll], ss[kUnroll];
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      if (h < a.n_half && ady <= a.half[h]) {
-        S[h] += v;
-        C[h] += 1;
-        Mx[h] = max(Mx[h], v);
+    for (int u = 0; u < kUnroll; ++u) {
+      const int y = yb + u;
+      const bool in = y >= ya && y <= yz;
+      vv[u] = in ? a.V[base + (int64_t)y * a.nx] : 0;
+      ss[u] = in ? a.state[base + (int64_t)y * a.nx] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int y = yb + u;
+      if (ss[u] == 0) continue;   // empty or outside this lane's slab
+      const int ady = y > d ? y - d : d - y;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        if (h < a.n_half && ady <= a.half[h]) {
+          S[h] += vv[u];
+          C[h] += 1;
+          Mx[h] = max(Mx[h], vv[u]);
+        }
       }
     }
   }
+  if (!active) return;
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     if (h < a.n_half) {
@@ -129,7 +189,7 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
 
 hipError_t launch_segment(const SegArgs &a, hipStream_t s) {
   if (a.mode == 0) {
-    hipLaunchKernelGGL(raw_depth_kernel, dim3((a.nx + 255) / 256, a.nz), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(raw_depth_kernel, dim3((a.nx + 63) / 64, a.nz), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
