@@ -265,6 +265,8 @@ def main():
     frames = torch.from_numpy(d["frames"]).cuda()
     vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
     pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+    # tile shape picked by the library's autotuner on the first 192 frames (untimed)
+    vol.autotune(pid, frames[:192], d["poses"][:192], None)
     tile = vol.tiling(pid)
     nx, ny, nz = g.dims
     V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")

@@ -203,8 +203,9 @@ usv_status usv_autotune(usv_volume *vol, int32_t probe_id, const uint8_t *frames
 usv_status usv_probe_tiling(const usv_volume *vol, int32_t probe_id, int32_t *tile_w, int32_t *tile_h);
 
 /* Force a probe's tile shape.  Supported shapes (w x h): 60x64, 64x48, 64x32, 32x64,
- * 32x32, 64x16, 128x8, 48x60, 40x48; anything else is USV_E_UNSUPPORTED.  Results do
- * not depend on the tiling (bit for bit), only the speed does. */
+ * 32x32, 64x16, 128x8, 48x60, 40x48, 60x128, 48x120, 64x64, 32x128, 128x16, 60x96,
+ * 120x64, 120x32, 240x16, 240x32, 240x8; anything else is USV_E_UNSUPPORTED.  Results
+ * do not depend on the tiling (bit for bit), only the speed does. */
 usv_status usv_probe_set_tiling(usv_volume *vol, int32_t probe_id, int32_t tile_w, int32_t tile_h);
 
 /* ---------------------------------------------------------------------------------

@@ -21,9 +21,11 @@ constexpr int TX = 64, TY = 16, RPW = 4, PX = TX + 2, PY = TY + 2, PLANE = PX * 
 constexpr int kHalo = 2 * PY + 2 * TX;   // halo words of a plane: two columns, two rows
 constexpr int kDepth = 3;                // planes of raw loads in flight per lane
 
-// floor(num / den) for num < 2^26, 0 < den < 2^18: approximate quotient, corrected once.
+// floor(num / den) for num < 2^26, 0 < den < 2^18 and a quotient below 2^9: the FP32
+// estimate num * rcp(den) has a relative error below 2^-21, so it is within one of the
+// quotient and one correction each way makes it exact.
 __device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t den) {
-  uint32_t q = (uint32_t)__fdividef((float)num, (float)den);
+  uint32_t q = (uint32_t)((float)num * __builtin_amdgcn_rcpf((float)den));
   int32_t r = (int32_t)num - (int32_t)(q * den);
   if (r < 0) --q;
   else if (r >= (int32_t)den) ++q;
@@ -44,7 +46,7 @@ struct Raw {
   uint32_t hs, hc;
 };
 
-__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
+__global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
   __shared__ uint32_t plane[2][PLANE];
   const int tid = threadIdx.x;
   const int tx = tid & (TX - 1), wv = tid >> 6;
@@ -54,6 +56,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
   const int64_t nxy = (int64_t)a.nx * a.ny;
   const int x = x0 + tx;
   const bool xin = x < a.nx;
+  // per-lane 32-bit offsets inside a plane (grids hold < 2^31 voxels); plane bases are uniform
+  uint32_t off[RPW];
+  uint32_t own = 0u;   // bit k: voxel k of this lane is in the grid
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int y = y0 + wv * RPW + k;
+    off[k] = (uint32_t)x + (uint32_t)a.nx * (uint32_t)y;
+    if (xin && y < a.ny) own |= 1u << k;
+  }
   // this lane's halo voxel (plane coordinates): left / right columns, then top / bottom rows
   int hpx = -1, hpy = -1;
   if (tid < 2 * PY) {
@@ -66,27 +77,24 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
   }
   const int hx = x0 - 1 + hpx, hy = y0 - 1 + hpy;
   const bool hin = hpx >= 0 && hx >= 0 && hx < a.nx && hy >= 0 && hy < a.ny;
-  const int64_t hoff = (int64_t)hx + (int64_t)a.nx * hy;
+  const uint32_t hoff = hin ? (uint32_t)hx + (uint32_t)a.nx * (uint32_t)hy : 0u;
 
+  // loads are unconditional (out-of-grid lanes read voxel 0 of the plane) and masked
+  // afterwards: no branches around them
   auto load = [&](int z, Raw &r) {
     const bool zin = z >= 0 && z < a.nz;
+    const uint32_t m = zin ? own : 0u;
+    const uint32_t hm = (zin && hin) ? ~0u : 0u;
+    const char *ps = reinterpret_cast<const char *>(a.sum + (zin ? nxy * z : 0));
+    const char *pc = reinterpret_cast<const char *>(a.cnt + (zin ? nxy * z : 0));
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
-      const int y = y0 + wv * RPW + k;
-      r.s[k] = 0u;
-      r.c[k] = 0u;
-      if (zin && xin && y < a.ny) {
-        const int64_t i = (int64_t)x + (int64_t)a.nx * y + nxy * z;
-        r.s[k] = a.sum[i];
-        r.c[k] = a.cnt[i];
-      }
+      const uint32_t mk = 0u - ((m >> k) & 1u);
+      r.s[k] = *reinterpret_cast<const uint32_t *>(ps + (size_t)((off[k] << 2) & mk)) & mk;
+      r.c[k] = *reinterpret_cast<const uint16_t *>(pc + (size_t)((off[k] << 1) & mk)) & mk;
     }
-    r.hs = 0u;
-    r.hc = 0u;
-    if (zin && hin) {
-      r.hs = a.sum[hoff + nxy * z];
-      r.hc = a.cnt[hoff + nxy * z];
-    }
+    r.hs = *reinterpret_cast<const uint32_t *>(ps + (size_t)((hoff << 2) & hm)) & hm;
+    r.hc = *reinterpret_cast<const uint16_t *>(pc + (size_t)((hoff << 1) & hm)) & hm;
   };
   auto store = [&](int slot, const Raw &r) {
     uint32_t *p = plane[slot];
@@ -129,11 +137,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
     __syncthreads();
     psum((z + 1) & 1, Pp, Cp);
     if (xin && x < a.hi[0]) {
+      uint8_t *pV = a.V + nxy * z;
+      uint8_t *pS = a.state ? a.state + nxy * z : nullptr;
 #pragma unroll
       for (int k = 0; k < RPW; ++k) {
         const int y = y0 + wv * RPW + k;
         if (y >= a.hi[1]) continue;
-        const int64_t i = (int64_t)x + (int64_t)a.nx * y + nxy * z;
+        const uint32_t i = off[k];
         uint32_t V, st;
         if (C0[k] >> 16) {
           V = C0[k] & 0xFFu;
@@ -149,8 +159,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
             st = 0u;
           }
         }
-        a.V[i] = (uint8_t)V;
-        if (a.state) a.state[i] = (uint8_t)st;
+        pV[i] = (uint8_t)V;
+        if (pS) pS[i] = (uint8_t)st;
       }
     }
 #pragma unroll

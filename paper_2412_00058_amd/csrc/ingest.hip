@@ -1,24 +1,30 @@
 // Pixel-nearest-neighbour compounding kernels for gfx950 (Sec. II.C: PNN distribution,
 // applied incrementally to newly acquired frames).
 //
-// Work unit: one tile (tw x th pixels) of one frame.  Blocks are persistent and walk
-// the (frame, tile row, tile column) list with a stride that is a multiple of the
-// tile-column count, so each block -- and, with the hardware's round-robin placement
-// of blocks on the 8 XCDs, each XCD's L2 -- keeps to one lateral stripe of the volume.
+// Work unit: one tile (tw x th pixels) of one frame per block.  Each pixel's voxel follows
+// the fixed FP32 order q_r = fl(fl(M[r][0] u) + fl(fl(M[r][1] v) + M[r][2])), kept iff
+// 0 <= q_r < n_r for all r, index = floor(q), x fastest.  Blocks are numbered (frame, tile
+// row, tile column) with the column fastest; the hardware places consecutive blocks on
+// the 8 XCDs in turn.
 //
-// Exactness of a tile's voxel window: q_r(u, v) = fl(fl(M0 u) + fl(fl(M1 v) + M2)) is
-// monotone in u and in v (IEEE rounding is monotone), so its extremes over a pixel
-// rectangle are reached at the corner chosen by the signs of M0 and M1, and the floors
-// of those extremes bound every voxel the tile can reach.
+// Exactness of a tile's voxel window: q_r(u, v) is monotone in u and in v (IEEE rounding
+// is monotone), so its extremes over a pixel rectangle are reached at the corner chosen
+// by the signs of M[r][0] and M[r][1], and the floors of those extremes bound every voxel
+// the tile can reach.
 //
-// Per tile: pixels are merged in an LDS window (one packed word per voxel: count <<
-// cshift | sum; cshift 20 for tiles of <= 4095 pixels, 19 for bigger tiles whose frames
-// put at most 2056 pixels in any voxel, which the host checks per frame), then the window is flushed with coalesced 32-bit global
-// atomics -- one for the uint32 sum and, for the uint16 counts, one per 32-bit word
-// holding two neighbouring voxels (paired through a DPP lane shift) -- and zeroed as it
-// is read, ready for the next tile.  Count atomics return the old word; the overflow
-// test on it is made after a batch of atomics is in flight.  The rows of the next tile
-// are loaded before the current window is flushed.
+// Per tile: the lane's pixel rows are loaded first; the LDS window (one packed word per
+// voxel, count << cshift | sum; cshift 20 for tiles of <= 4095 pixels, 19 for bigger tiles
+// whose frames the host has checked to put at most 2056 pixels in any voxel) is zeroed
+// and a table of per-row constants built; every pixel adds one LDS atomic; the window
+// is then flushed with global atomics -- with an even grid width, both u32 sums of a voxel
+// pair with one 64-bit atomic and both u16 counts with one 32-bit atomic.  No atomic
+// returns a value: a wrapped u16 count is found afterwards by comparing the sum of the
+// stored counts with the kept-pixel total.
+//
+// Cost model (measured): device-scope atomics are performed beyond the XCD's L2, one
+// request per 64-byte segment a wave instruction touches, at ~25 G requests/s; a tilted
+// frame crosses each voxel row in runs of ~1 / tan(tilt) voxels, so the flush costs about
+// two requests per run and dominates the kernel.  Wider tiles split fewer runs.
 #include "usv_internal.h"
 
 namespace usv {
@@ -430,18 +436,29 @@ __global__ __launch_bounds__(256) void count_sum_kernel(const uint32_t *__restri
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void count_final_kernel(const unsigned long long *__restrict__ partials, int n_partials,
-                                   unsigned long long *__restrict__ kept, uint32_t *__restrict__ err, int store) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(256) void count_final_kernel(const unsigned long long *__restrict__ partials,
+                                                          int n_partials, unsigned long long *__restrict__ kept,
+                                                          uint32_t *__restrict__ err, int store) {
+  __shared__ unsigned long long red[2][4];
   unsigned long long stored = 0ull, added = 0ull;
-  for (int i = 0; i < n_partials; ++i) stored += partials[i];
+  for (int i = threadIdx.x; i < n_partials; i += 256) stored += partials[i];
+  for (int i = threadIdx.x; i < kKeptSlots; i += 256) added += kept[i];
+  for (int o = 32; o > 0; o >>= 1) {
+    stored += __shfl_xor(stored, o);
+    added += __shfl_xor(added, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = stored;
+    red[1][threadIdx.x >> 6] = added;
+  }
+  __syncthreads();
+  stored = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  added = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   if (store) {
-    kept[0] = stored;
-    for (int i = 1; i < kKeptSlots; ++i) kept[i] = 0ull;
+    for (int i = threadIdx.x; i < kKeptSlots; i += 256) kept[i] = i == 0 ? stored : 0ull;
     return;
   }
-  for (int i = 0; i < kKeptSlots; ++i) added += kept[i];
-  if (stored != added) err[0] = 1u;
+  if (threadIdx.x == 0 && stored != added) err[0] = 1u;
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
@@ -494,7 +511,7 @@ hipError_t launch_count_check(const uint32_t *cnt32, int64_t n_words, unsigned l
   hipLaunchKernelGGL(count_sum_kernel, dim3(kCheckBlocks), dim3(256), 0, s, cnt32, n_words, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(count_final_kernel, dim3(1), dim3(64), 0, s, partials, kCheckBlocks, kept, err, store ? 1 : 0);
+  hipLaunchKernelGGL(count_final_kernel, dim3(1), dim3(256), 0, s, partials, kCheckBlocks, kept, err, store ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -224,7 +224,8 @@ struct TileCand {
   int lr, kr;
 };
 const TileCand kCands[] = {{15, 4}, {16, 3}, {16, 2}, {8, 2}, {8, 1}, {16, 1}, {32, 1}, {12, 3}, {10, 2},
-                           {15, 8}, {12, 6}, {16, 4}, {8, 4}, {32, 2}, {15, 6}};
+                           {15, 8}, {12, 6}, {16, 4}, {8, 4}, {32, 2}, {15, 6},
+                           {30, 8}, {30, 4}, {60, 4}, {60, 8}, {60, 2}};
 
 Tiling make_tiling(int lr, int kr, int W, int H) {
   Tiling t{};
@@ -245,12 +246,14 @@ Tiling make_tiling(int lr, int kr, int W, int H) {
 }
 
 bool tiling_valid(const Tiling &t) {
-  return t.tw * t.th <= kMaxTilePixels && t.th <= kMaxTileRows && t.lr >= 2 && t.lr <= 32 && t.rpw >= 1;
+  return t.tw * t.th <= kMaxTilePixels && t.th <= kMaxTileRows && t.lr >= 2 && t.lr <= 64 && t.rpw >= 1;
 }
 
 // Heuristic default: largest tile whose planar footprint fits comfortably in the LDS
-// window, preferring a tile-column count that is a multiple of the 8 XCDs.  small: only
-// tilings of <= 4095 pixels (always exact with the 20-bit sum field).
+// window, preferring widths up to 120 pixels (a tilted frame crosses voxel rows in
+// runs; wider tiles cut fewer of them, so the flush needs fewer atomic requests) and
+// little padding at the image edge.  small: only tilings of <= 4095 pixels (always exact
+// with the 20-bit sum field).  usv_autotune replaces this by measurement.
 Tiling default_tiling(const ProbeState &p, double voxel, bool small) {
   Tiling best{};
   double best_score = -1.0;
@@ -261,8 +264,7 @@ Tiling default_tiling(const ProbeState &p, double voxel, bool small) {
     const double ex = t.tw * p.sx / voxel + 2.0, ey = t.th * p.sy / voxel + 2.0;
     const double est = ex * ey * 3.0;
     if (est > 0.6 * kWinMax) continue;
-    double score = (double)(t.tw * t.th);
-    if (t.tiles_x % 8 == 0) score *= 1.25;
+    double score = (double)(t.tw * t.th) * (1.0 + (double)std::min(t.tw, 120) / 120.0);
     const int wasted = t.tiles_x * t.tw - p.W;
     score *= 1.0 - 0.5 * (double)wasted / (double)(t.tiles_x * t.tw);
     if (score > best_score) {

@@ -11,7 +11,8 @@ from gpu_util import add_probe, assert_accum_equal, gpu_volume, oracle_accum, sa
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(60, 64), (64, 48), (64, 32), (32, 64), (32, 32), (64, 16), (128, 8), (48, 60), (40, 48),
-          (128, 16), (60, 128), (48, 120), (64, 64), (32, 128), (60, 96)]
+          (128, 16), (60, 128), (48, 120), (64, 64), (32, 128), (60, 96),
+          (120, 64), (120, 32), (240, 16), (240, 32), (240, 8)]
 BIG_SHAPES = [sh for sh in SHAPES if sh[0] * sh[1] > 4095]
 
 
