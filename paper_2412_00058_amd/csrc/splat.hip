@@ -2,10 +2,11 @@
 // refinement against patient motion).
 //   splat_pose_kernel    : per frame T = Exp(xi) T* (FP64, Rodrigues form), the FP64
 //                          pixel -> (voxel coordinate - 1/2) map and J_l(xi)^T (series
-//                          sum_k ad(xi)^k / (k+1)!);
+//                          sum_k ad(xi)^k / (k+1)!, one thread per entry);
 //   splat_fwd_kernel     : one block per 32x32 pixel tile; FP64 coordinates, FP32 corner
-//                          weights, merged in an LDS window of (S, W) pairs, flushed with
-//                          FP32 global atomics into the frame's set (even / odd frames);
+//                          weights, merged in an LDS window of 64-bit fixed-point (S, W)
+//                          pairs, flushed with FP32 global atomics into the frame's set
+//                          (even / odd frames);
 //   loss_kernel          : R = S_A W_B - S_B W_A, 1/2 sum R^2 (FP64 block partials) and
 //                          the four volume gradients;
 //   splat_bwd_kernel     : recomputes the weights, gathers the gradient volumes, writes
@@ -20,82 +21,87 @@ namespace usv {
 namespace {
 
 constexpr int STW = 32, STH = 32;
-constexpr int kSplatWin = 3072;   // (S, W) pairs per block: 24 KiB
+constexpr int kSplatWin = 2816;   // (S, W) fixed-point pairs per block: 44 KiB
 
 __device__ void mat3_mul(const double *a, const double *b, double *c) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) c[i * 3 + j] = a[i * 3] * b[j] + a[i * 3 + 1] * b[3 + j] + a[i * 3 + 2] * b[6 + j];
 }
 
-__global__ void splat_pose_kernel(SplatGeom g, const double *__restrict__ Tstar, const double *__restrict__ xi, int F,
-                                  double *__restrict__ Mq, double *__restrict__ Jt) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= F) return;
+// One block of 64 threads per frame.  Thread 0 forms T = Exp(xi) T* and the map; the 36
+// entries of J_l(xi) = sum_k ad^k / (k+1)! are owned by threads 0 .. 35, each adding its
+// entry of ad^k / (k+1)! per term (the power ad^k passes through LDS).
+__global__ __launch_bounds__(64) void splat_pose_kernel(SplatGeom g, const double *__restrict__ Tstar,
+                                                        const double *__restrict__ xi, int F, double *__restrict__ Mq,
+                                                        double *__restrict__ Jt) {
+  __shared__ double ad[36], Pk[2][36];
+  const int n = blockIdx.x;
+  const int t = threadIdx.x;
   const double *x = xi + 6 * n;
   const double w0 = x[3], w1 = x[4], w2 = x[5];
-  const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
-  double A, B, C;
-  if (th < 1e-3) {
-    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
-  } else {
-    A = sin(th) / th;
-    B = (1.0 - cos(th)) / th2;
-    C = (th - sin(th)) / (th2 * th);
-  }
   const double W[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
-  double W2[9];
-  mat3_mul(W, W, W2);
-  double R[9], V[9];
-  for (int i = 0; i < 9; ++i) {
-    const double I = (i % 4 == 0) ? 1.0 : 0.0;
-    R[i] = I + A * W[i] + B * W2[i];
-    V[i] = I + B * W[i] + C * W2[i];
-  }
-  double t[3];
-  for (int i = 0; i < 3; ++i) t[i] = V[i * 3] * x[0] + V[i * 3 + 1] * x[1] + V[i * 3 + 2] * x[2];
-  const double *Ts = Tstar + 16 * n;
-  const double o[3] = {g.origin[0], g.origin[1], g.origin[2]};
-  for (int r = 0; r < 3; ++r) {
-    double T[4];
-    for (int c = 0; c < 4; ++c)
-      T[c] = R[r * 3] * Ts[c] + R[r * 3 + 1] * Ts[4 + c] + R[r * 3 + 2] * Ts[8 + c] + t[r] * Ts[12 + c];
-    // (x - o) / s - 1/2 as an affine map of the pixel index (u, v)
-    Mq[9 * n + 3 * r + 0] = T[0] * g.sx / g.s;
-    Mq[9 * n + 3 * r + 1] = T[1] * g.sy / g.s;
-    Mq[9 * n + 3 * r + 2] = (T[3] + 0.5 * g.sx * T[0] + 0.5 * g.sy * T[1] - o[r]) / g.s - 0.5;
-  }
-  // J_l(xi) = sum_k ad^k / (k+1)!, ad = [[w^, rho^], [0, w^]]
-  double ad[36] = {0};
-  const double P[9] = {0.0, -x[2], x[1], x[2], 0.0, -x[0], -x[1], x[0], 0.0};
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      ad[i * 6 + j] = W[i * 3 + j];
-      ad[i * 6 + 3 + j] = P[i * 3 + j];
-      ad[(3 + i) * 6 + 3 + j] = W[i * 3 + j];
+  if (t == 0) {
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-3) {
+      A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+      B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+      C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+      A = sin(th) / th;
+      B = (1.0 - cos(th)) / th2;
+      C = (th - sin(th)) / (th2 * th);
     }
-  double J[36], Pk[36], Q[36];
-  for (int i = 0; i < 36; ++i) {
-    Pk[i] = (i % 7 == 0) ? 1.0 : 0.0;
-    J[i] = Pk[i];
+    double W2[9];
+    mat3_mul(W, W, W2);
+    double R[9], V[9];
+    for (int i = 0; i < 9; ++i) {
+      const double Id = (i % 4 == 0) ? 1.0 : 0.0;
+      R[i] = Id + A * W[i] + B * W2[i];
+      V[i] = Id + B * W[i] + C * W2[i];
+    }
+    double tr[3];
+    for (int i = 0; i < 3; ++i) tr[i] = V[i * 3] * x[0] + V[i * 3 + 1] * x[1] + V[i * 3 + 2] * x[2];
+    const double *Ts = Tstar + 16 * n;
+    const double o[3] = {g.origin[0], g.origin[1], g.origin[2]};
+    for (int r = 0; r < 3; ++r) {
+      double T[4];
+      for (int c = 0; c < 4; ++c)
+        T[c] = R[r * 3] * Ts[c] + R[r * 3 + 1] * Ts[4 + c] + R[r * 3 + 2] * Ts[8 + c] + tr[r] * Ts[12 + c];
+      // (x - o) / s - 1/2 as an affine map of the pixel index (u, v)
+      Mq[9 * n + 3 * r + 0] = T[0] * g.sx / g.s;
+      Mq[9 * n + 3 * r + 1] = T[1] * g.sy / g.s;
+      Mq[9 * n + 3 * r + 2] = (T[3] + 0.5 * g.sx * T[0] + 0.5 * g.sy * T[1] - o[r]) / g.s - 0.5;
+    }
   }
+  // J_l(xi): ad = [[w^, rho^], [0, w^]]
+  const int i = t / 6, j = t - 6 * (t / 6);
+  double J = 0.0;
+  if (t < 36) {
+    const double P[9] = {0.0, -x[2], x[1], x[2], 0.0, -x[0], -x[1], x[0], 0.0};
+    double a = 0.0;
+    if (i < 3 && j < 3) a = W[i * 3 + j];
+    else if (i < 3) a = P[i * 3 + j - 3];
+    else if (j >= 3) a = W[(i - 3) * 3 + j - 3];
+    ad[t] = a;
+    J = (i == j) ? 1.0 : 0.0;
+    Pk[0][t] = J;
+  }
+  __syncthreads();
   double fact = 1.0;
+  int cur = 0;
   for (int k = 1; k <= 26; ++k) {
-    for (int i = 0; i < 6; ++i)
-      for (int j = 0; j < 6; ++j) {
-        double acc = 0.0;
-        for (int l = 0; l < 6; ++l) acc += Pk[i * 6 + l] * ad[l * 6 + j];
-        Q[i * 6 + j] = acc;
-      }
-    fact *= (double)(k + 1);
-    for (int i = 0; i < 36; ++i) {
-      Pk[i] = Q[i];
-      J[i] += Q[i] / fact;
+    if (t < 36) {
+      double acc = 0.0;
+      for (int l = 0; l < 6; ++l) acc += Pk[cur][i * 6 + l] * ad[l * 6 + j];
+      fact *= (double)(k + 1);
+      Pk[cur ^ 1][t] = acc;
+      J += acc / fact;
     }
+    cur ^= 1;
+    __syncthreads();
   }
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) Jt[36 * n + i * 6 + j] = J[j * 6 + i];
+  if (t < 36) Jt[36 * n + j * 6 + i] = J;
 }
 
 // voxel window of a pixel tile: p is affine in (u, v), so its range over the tile is
@@ -135,9 +141,16 @@ __device__ __forceinline__ void pixel_coord(const double *m, int u, int v, const
   }
 }
 
+// Forward splat of one 32x32 pixel tile.  Contributions are merged in the LDS window as
+// 64-bit fixed-point integers (integer LDS atomics are several times faster than FP32
+// ones on gfx950): W with 2^-52 units (a voxel takes at most 1024 weights <= 1), S with
+// 2^-(52 - e) units where 2^e bounds |I| over the tile, so no sum can reach 2^62 and each
+// contribution is rounded by at most 2^-53 of the tile's largest |I|.  The window is
+// flushed with FP32 global atomics of the converted sums.
 __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float *__restrict__ I,
                                                         const double *__restrict__ Mq, float *__restrict__ vols) {
-  __shared__ __align__(16) float2 win[kSplatWin];
+  __shared__ __align__(16) unsigned long long win[2 * kSplatWin];   // (S, W) of entry e at 2e, 2e + 1
+  __shared__ float red[4];
   const int b = blockIdx.x;
   const int tc = b % g.tiles_x, rest = b / g.tiles_x;
   const int tr = rest % g.tiles_y, f = rest / g.tiles_y;
@@ -158,14 +171,31 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float
   const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
   float *S = vols + (int64_t)(f & 1) * 2 * nvox;
   float *Wt = S + nvox;
-  for (int e = threadIdx.x; e < we; e += 256) win[e] = make_float2(0.0f, 0.0f);
-  __syncthreads();
   const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
   const int u = u0 + tx;
-  for (int ty = ty0; ty < STH; ty += 8) {
-    const int v = v0 + ty;
+  // this lane's four pixels, and the tile's largest |I|
+  float val[STH / 8];
+  float amax = 0.0f;
+#pragma unroll
+  for (int k = 0; k < STH / 8; ++k) {
+    const int v = v0 + ty0 + 8 * k;
+    val[k] = (u <= u1 && v <= v1) ? I[((int64_t)f * g.H + v) * g.W + u] : 0.0f;
+    amax = fmaxf(amax, fabsf(val[k]));
+  }
+  for (int e = threadIdx.x; e < 2 * we; e += 256) win[e] = 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  int ex = 0;
+  if (amax > 0.0f && amax <= 3.0e38f) (void)frexpf(amax, &ex);   // |I| < 2^ex
+  const int ks = min(127, max(-126, 52 - ex));   // scale exponent of S (a normal float)
+  const float sc_s = ldexpf(1.0f, ks), sc_w = ldexpf(1.0f, 52);
+#pragma unroll
+  for (int k = 0; k < STH / 8; ++k) {
+    const int v = v0 + ty0 + 8 * k;
     if (u > u1 || v > v1) continue;
-    const float val = I[((int64_t)f * g.H + v) * g.W + u];
     PixW p;
     double pd[3];
     pixel_coord(m, u, v, g, p, pd);
@@ -177,28 +207,29 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float
       const int cx = p.i0[0] + bx, cy = p.i0[1] + by, cz = p.i0[2] + bz;
       if (!direct) {
         const int e = (cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2]));
-        atomicAdd(&win[e].x, w * val);
-        atomicAdd(&win[e].y, w);
+        atomicAdd(&win[2 * e], (unsigned long long)__float2ll_rn((w * val[k]) * sc_s));
+        atomicAdd(&win[2 * e + 1], (unsigned long long)__float2ll_rn(w * sc_w));
       } else {
         const int64_t gi = (int64_t)cx + (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
-        atomicAdd(S + gi, w * val);
+        atomicAdd(S + gi, w * val[k]);
         atomicAdd(Wt + gi, w);
       }
     }
   }
   __syncthreads();
   if (direct) return;
+  const double inv_s = ldexp(1.0, -ks), inv_w = ldexp(1.0, -52);
   const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
   for (int e = threadIdx.x; e < we; e += 256) {
-    const float2 sw = win[e];
-    if (sw.x == 0.0f && sw.y == 0.0f) continue;
+    const ulonglong2 sw = *reinterpret_cast<const ulonglong2 *>(&win[2 * e]);
+    if (sw.x == 0ull && sw.y == 0ull) continue;
     const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
-    const int ex = e - r1 * wx;
+    const int ix = e - r1 * wx;
     const int ez = wy == 1 ? r1 : (int)__umulhi((uint32_t)r1, mag_wy);
     const int ey = r1 - ez * wy;
-    const int64_t gi = (int64_t)(lo[0] + ex) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
-    atomicAdd(S + gi, sw.x);
-    atomicAdd(Wt + gi, sw.y);
+    const int64_t gi = (int64_t)(lo[0] + ix) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
+    atomicAdd(S + gi, (float)((double)(long long)sw.x * inv_s));
+    atomicAdd(Wt + gi, (float)((double)(long long)sw.y * inv_w));
   }
 }
 
@@ -234,12 +265,15 @@ __global__ __launch_bounds__(256) void loss_kernel(int64_t nvox, const float *__
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ void sum_partials_kernel(const double *__restrict__ partial, int n, double *__restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < n; ++i) t += partial[i];
-    out[0] = t;
-  }
+// Sum of the block partials in a fixed order (deterministic): strided per-thread sums,
+// then a fixed tree.
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restrict__ partial, int n,
+                                                           double *__restrict__ out) {
+  __shared__ double sh[4];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) t += partial[i];
+  t = block_sum_d(t, sh);
+  if (threadIdx.x == 0) out[0] = t;
 }
 
 __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float *__restrict__ I,
@@ -348,7 +382,7 @@ __global__ void frame_reduce_kernel(SplatGeom g, const double *__restrict__ Mq, 
 hipError_t launch_splat_pose(const SplatGeom &g, const double *Tstar, const double *xi, int F, double *Mq, double *Jt,
                              hipStream_t s) {
   if (F <= 0) return hipSuccess;
-  hipLaunchKernelGGL(splat_pose_kernel, dim3((F + 63) / 64), dim3(64), 0, s, g, Tstar, xi, F, Mq, Jt);
+  hipLaunchKernelGGL(splat_pose_kernel, dim3(F), dim3(64), 0, s, g, Tstar, xi, F, Mq, Jt);
   return hipGetLastError();
 }
 
@@ -367,7 +401,7 @@ hipError_t launch_overlap_loss(int64_t nvox, const float *vols, float *grads, do
   hipLaunchKernelGGL(loss_kernel, dim3(n_partial), dim3(256), 0, s, nvox, vols, grads, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partial, n_partial, loss);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, n_partial, loss);
   return hipGetLastError();
 }
 
