@@ -12,7 +12,8 @@ of accumulator read/write per distinct voxel touched by the launch, counted by t
 oracle) divided by the launch duration measured with HIP events on the library's stream.
 `cpu_baseline` times the CPU oracle on the same step on one host core.
 Beside the main line: differentiable splat forward+backward frames/s (512 frames of
-320 x 240 into 256 x 192 x 512) and batched 16-sweep ingest frames/s.
+320 x 240 into 256 x 192 x 512), single-frame captured-graph ingest from host memory
+(frames/s back to back, p50/p99 latency) and batched 16-sweep ingest frames/s.
 """
 from __future__ import annotations
 
@@ -172,6 +173,43 @@ def bench_splat(torch, usv, steps):
     dt = (time.perf_counter() - t0) / steps
     ctx.close()
     return F / dt, dt * 1e3
+
+
+def bench_graph(torch, usv, d, n=512, n_lat=200):
+    """Real-time path: one frame per captured-graph launch from host memory (pinned
+    staging copy, H2D, ingest).  Returns (frames/s back to back, p50 and p99 latency in
+    ms of launch + completion for single frames)."""
+    g, p = d["grid"], d["probe"]
+    vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+    pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+    gr = usv.Graph(vol, pid)
+    L = usv.lib()
+    n = min(n, d["frames"].shape[0])
+    fr = np.ascontiguousarray(d["frames"][:n])
+    P = np.ascontiguousarray(d["poses"][:n].reshape(n, 16))
+    fp = [C.c_void_p(fr[i].ctypes.data) for i in range(n)]
+    pp = [C.c_void_p(P[i].ctypes.data) for i in range(n)]
+    stream = torch.cuda.current_stream()
+    for i in range(16):
+        L.usv_graph_launch(gr.h, fp[i], pp[i], None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n):
+        if L.usv_graph_launch(gr.h, fp[i], pp[i], None) != 0:
+            raise RuntimeError("graph launch failed")
+    torch.cuda.synchronize()
+    rate = n / (time.perf_counter() - t0)
+    lat = []
+    for i in range(n_lat):
+        t = time.perf_counter()
+        L.usv_graph_launch(gr.h, fp[i % n], pp[i % n], None)
+        stream.synchronize()
+        lat.append(time.perf_counter() - t)
+    gr.close()
+    if vol.status() != 0:
+        raise RuntimeError("graph ingest reported an error")
+    lat = np.sort(np.array(lat)) * 1e3
+    return rate, float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
 def bench_batched(torch, usv, steps):
@@ -365,6 +403,13 @@ def main():
             extras["fwd_bwd_ms_per_step"] = round(ms, 3)
         except Exception as e:  # report, do not hide
             extras["fwd_bwd_error"] = repr(e)
+        try:
+            rate, p50, p99 = bench_graph(torch, usv, d)
+            extras["graph_frames_per_s"] = round(rate, 1)
+            extras["graph_latency_ms_p50"] = round(p50, 4)
+            extras["graph_latency_ms_p99"] = round(p99, 4)
+        except Exception as e:
+            extras["graph_error"] = repr(e)
         try:
             fps, ms, tot = bench_batched(torch, usv, max(2, min(args.steps, 5)))
             extras["batched_frames_per_s"] = round(fps, 1)

@@ -276,9 +276,14 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restr
   if (threadIdx.x == 0) out[0] = t;
 }
 
+// Backward of one 32x32 pixel tile.  The tile's voxel window of the frame set's two
+// gradient volumes (dL/dS, dL/dW) is staged in LDS with coalesced row loads, so the 8
+// corner gathers of each pixel are LDS reads; windows too large for LDS gather from
+// global memory.
 __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float *__restrict__ I,
                                                         const double *__restrict__ Mq, const float *__restrict__ grads,
                                                         float *__restrict__ dI, double *__restrict__ partial) {
+  __shared__ __align__(16) float2 gwin[kSplatWin];
   __shared__ float red[6][4];
   const int b = blockIdx.x;
   const int tc = b % g.tiles_x, rest = b / g.tiles_x;
@@ -293,12 +298,36 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   const float *GS = grads + (int64_t)(f & 1) * 2 * nvox;
   const float *GW = GS + nvox;
   const int u0 = tc * STW, v0 = tr * STH;
+  const int u1 = min(u0 + STW, g.W) - 1, v1 = min(v0 + STH, g.H) - 1;
+  // voxel window of the tile (as in the forward); staged = it fits in LDS
+  int lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+  const double du0 = u0, du1 = u1, dv0 = v0, dv1 = v1;
+  bool any = splat_axis(m, du0, du1, dv0, dv1, g.nx, lo[0], hi[0]);
+  any = any && splat_axis(m + 3, du0, du1, dv0, dv1, g.ny, lo[1], hi[1]);
+  any = any && splat_axis(m + 6, du0, du1, dv0, dv1, g.nz, lo[2], hi[2]);
+  const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
+  const int64_t we64 = any ? (int64_t)wx * wy * wz : 0;
+  const bool staged = any && we64 <= kSplatWin;
+  if (staged) {
+    // one window row (wx voxels along x) per group of lanes; rows are contiguous in HBM
+    const int we = (int)we64;
+    const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
+    for (int e = threadIdx.x; e < we; e += 256) {
+      const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
+      const int ix = e - r1 * wx;
+      const int ez = wy == 1 ? r1 : (int)__umulhi((uint32_t)r1, mag_wy);
+      const int ey = r1 - ez * wy;
+      const int64_t gi = (int64_t)(lo[0] + ix) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
+      gwin[e] = make_float2(GS[gi], GW[gi]);
+    }
+  }
+  __syncthreads();
   const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
   const int u = u0 + tx;
   float acc[6] = {0, 0, 0, 0, 0, 0};
   for (int ty = ty0; ty < STH; ty += 8) {
     const int v = v0 + ty;
-    if (u >= g.W || v >= g.H) continue;
+    if (!any || u > u1 || v > v1) continue;
     const int64_t pix = ((int64_t)f * g.H + v) * g.W + u;
     const float val = I[pix];
     PixW p;
@@ -312,8 +341,17 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
       const float fx = bx ? p.f[0] : 1.0f - p.f[0];
       const float fy = by ? p.f[1] : 1.0f - p.f[1];
       const float fz = bz ? p.f[2] : 1.0f - p.f[2];
-      const int64_t gi = (int64_t)(p.i0[0] + bx) + (int64_t)g.nx * ((int64_t)(p.i0[1] + by) + (int64_t)g.ny * (p.i0[2] + bz));
-      const float gs = GS[gi], gw = GW[gi];
+      const int cx = p.i0[0] + bx, cy = p.i0[1] + by, cz = p.i0[2] + bz;
+      float gs, gw;
+      if (staged) {
+        const float2 gg = gwin[(cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2]))];
+        gs = gg.x;
+        gw = gg.y;
+      } else {
+        const int64_t gi = (int64_t)cx + (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
+        gs = GS[gi];
+        gw = GW[gi];
+      }
       di += fx * fy * fz * gs;
       const float coef = val * gs + gw;
       gq[0] += coef * (bx ? 1.0f : -1.0f) * fy * fz;
@@ -328,6 +366,13 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
     acc[3] += ry * gq[2] - rz * gq[1];
     acc[4] += rz * gq[0] - rx * gq[2];
     acc[5] += rx * gq[1] - ry * gq[0];
+  }
+  // pixels of a tile outside the grid still get dL/dI = 0
+  if (!any) {
+    for (int ty = ty0; ty < STH; ty += 8) {
+      const int v = v0 + ty;
+      if (u <= u1 && v <= v1) dI[((int64_t)f * g.H + v) * g.W + u] = 0.0f;
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
