@@ -303,8 +303,10 @@ def main():
     frames = torch.from_numpy(d["frames"]).cuda()
     vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
     pid = vol.add_probe(p.width, p.height, p.pixel_mm)
-    # tile shape picked by the library's autotuner on the first 192 frames (untimed)
-    vol.autotune(pid, frames[:192], d["poses"][:192], None)
+    # tile shape picked by the library's autotuner on the first 1024 frames (untimed); the
+    # choice is cached in a temp file so that profiled passes reuse it without re-tuning
+    import tempfile
+    vol.autotune(pid, frames[:1024], d["poses"][:1024], os.path.join(tempfile.gettempdir(), "usv_bench_tune.txt"))
     tile = vol.tiling(pid)
     nx, ny, nz = g.dims
     V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")

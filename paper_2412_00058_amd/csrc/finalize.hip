@@ -20,6 +20,7 @@ namespace {
 constexpr int TX = 64, TY = 16, RPW = 4, PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
 constexpr int kHalo = 2 * PY + 2 * TX;   // halo words of a plane: two columns, two rows
 constexpr int kDepth = 3;                // planes of raw loads in flight per lane
+static_assert(kHalo <= 256, "one halo word per thread");
 
 // floor(num / den) for num < 2^26, 0 < den < 2^18 and a quotient below 2^9: the FP32
 // estimate num * rcp(den) has a relative error below 2^-21, so it is within one of the
@@ -50,8 +51,16 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
   __shared__ uint32_t plane[2][PLANE];
   const int tid = threadIdx.x;
   const int tx = tid & (TX - 1), wv = tid >> 6;
-  const int x0 = a.lo[0] + blockIdx.x * TX, y0 = a.lo[1] + blockIdx.y * TY;
-  const int zs = a.lo[2] + blockIdx.z * a.zchunk;
+  // XCD-aware block order: the hardware deals blocks to the 8 XCDs in turn, so block L
+  // runs on XCD L % 8.  Each XCD gets a contiguous range of (y, z) bands and runs all x
+  // blocks of a band back to back, so the cache lines that neighbouring blocks share
+  // (row ends, halo rows) are fetched into one L2 instead of two.
+  const int L = blockIdx.x, xcd = L & 7, j = L >> 3;
+  const int band = xcd * a.bands_per_xcd + j / a.gx;
+  if (band >= a.gy * a.gz) return;   // padding block
+  const int bx = j - (j / a.gx) * a.gx, by = band % a.gy, bz = band / a.gy;
+  const int x0 = a.lo[0] + bx * TX, y0 = a.lo[1] + by * TY;
+  const int zs = a.lo[2] + bz * a.zchunk;
   const int ze = min(zs + a.zchunk, a.hi[2]);
   const int64_t nxy = (int64_t)a.nx * a.ny;
   const int x = x0 + tx;
@@ -182,12 +191,16 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
 
 }  // namespace
 
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
-  const int ex = a.hi[0] - a.lo[0], ey = a.hi[1] - a.lo[1], ez = a.hi[2] - a.lo[2];
+hipError_t launch_finalize(const FinalizeArgs &args, hipStream_t s) {
+  const int ex = args.hi[0] - args.lo[0], ey = args.hi[1] - args.lo[1], ez = args.hi[2] - args.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
-  dim3 grid((ex + TX - 1) / TX, (ey + TY - 1) / TY, (ez + a.zchunk - 1) / a.zchunk);
-  static_assert(kHalo <= 256, "one halo word per thread");
-  hipLaunchKernelGGL(finalize_kernel, grid, dim3(256), 0, s, a);
+  FinalizeArgs a = args;
+  a.gx = (ex + TX - 1) / TX;
+  a.gy = (ey + TY - 1) / TY;
+  a.gz = (ez + a.zchunk - 1) / a.zchunk;
+  a.bands_per_xcd = (a.gy * a.gz + 7) / 8;
+  const int64_t blocks = (int64_t)8 * a.bands_per_xcd * a.gx;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

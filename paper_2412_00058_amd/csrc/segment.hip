@@ -18,11 +18,24 @@ namespace {
 // deepest, and the four segment winners are combined with ties to the deeper segment.
 constexpr int kSeg = 4, kUnroll = 8;
 
+// XCD-aware block order over a (gx x nbands) grid: block L runs on XCD L % 8; each XCD
+// takes a contiguous range of bands and all gx blocks of a band back to back, so lines
+// shared by x-neighbouring blocks are fetched into one L2.  Returns false for padding.
+__device__ __forceinline__ bool xcd_block(int gx, int nbands, int &bx, int &band) {
+  const int L = blockIdx.x, xcd = L & 7, j = L >> 3;
+  const int per = (nbands + 7) / 8;
+  band = xcd * per + j / gx;
+  bx = j - (j / gx) * gx;
+  return band < nbands;
+}
+__host__ __forceinline__ unsigned xcd_blocks(int gx, int nbands) { return (unsigned)(8 * ((nbands + 7) / 8) * gx); }
+
 __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
   __shared__ int32_t best_s_sh[kSeg][64], best_y_sh[kSeg][64];
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
-  const int x = blockIdx.x * 64 + lane;
-  const int z = blockIdx.y;
+  int bx, z;
+  if (!xcd_block((a.nx + 63) / 64, a.nz, bx, z)) return;   // uniform per block
+  const int x = bx * 64 + lane;
   const int64_t nxy = (int64_t)a.nx * a.ny;
   const int ymax = a.ny - 1 - a.k;
   int best = -1, best_s = 0;
@@ -91,12 +104,14 @@ __device__ __forceinline__ int wave_max(int v) {
 __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
   __shared__ int16_t tile[(SZ + 2 * RMAX) * (SX + 2 * RMAX)];
   const int tx = threadIdx.x & (SX - 1), tz = threadIdx.x >> 6;
-  const int x = blockIdx.x * SX + tx, z = blockIdx.y * SZ + tz;
+  int bx, bz;
+  if (!xcd_block((a.nx + SX - 1) / SX, (a.nz + SZ - 1) / SZ, bx, bz)) return;   // uniform per block
+  const int x = bx * SX + tx, z = bz * SZ + tz;
   const bool active = x < a.nx && z < a.nz;
   int d = 0;
   if (a.mode == 0) {
     const int r = a.r, pw = SX + 2 * r, ph = SZ + 2 * r;
-    const int xb = blockIdx.x * SX - r, zb = blockIdx.y * SZ - r;
+    const int xb = bx * SX - r, zb = bz * SZ - r;
     for (int e = threadIdx.x; e < pw * ph; e += 256) {
       const int pz = e / pw, px = e - pz * pw;
       const int gx = xb + px, gz = zb + pz;
@@ -189,11 +204,12 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
 
 hipError_t launch_segment(const SegArgs &a, hipStream_t s) {
   if (a.mode == 0) {
-    hipLaunchKernelGGL(raw_depth_kernel, dim3((a.nx + 63) / 64, a.nz), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(raw_depth_kernel, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(depth_slab_kernel, dim3((a.nx + SX - 1) / SX, (a.nz + SZ - 1) / SZ), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(depth_slab_kernel, dim3(xcd_blocks((a.nx + SX - 1) / SX, (a.nz + SZ - 1) / SZ)), dim3(256), 0, s,
+                     a);
   return hipGetLastError();
 }
 

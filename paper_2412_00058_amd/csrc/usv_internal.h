@@ -97,6 +97,7 @@ struct FinalizeArgs {
   int32_t fill_min;
   int32_t lo[3], hi[3];  // output box [lo, hi) (already dilated and clipped)
   int32_t zchunk;
+  int32_t gx, gy, gz, bands_per_xcd;   // block grid (set by launch_finalize)
 };
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
