@@ -1,0 +1,128 @@
+"""Edge cases of the nearest-voxel path on the GPU (empty calls, frames that miss the grid,
+masked probes through graphs, zero-frame sweeps in a batch) and the whole-spine sweep at
+full size in the benchmark's launch configuration, all against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import add_probe, assert_accum_equal, gpu_volume, oracle_accum, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _empty(box):
+    return any(box.lo[k] >= box.hi[k] for k in range(3))
+
+
+def test_empty_calls_change_nothing():
+    from paper_2412_00058_amd import Box
+    say("case: empty calls")
+    d = synth.cfg1()
+    vol = gpu_volume(d["grid"])
+    pid = add_probe(vol, d["probe"])
+    fr = to_dev(d["frames"])
+    vol.ingest(pid, fr[:20], d["poses"][:20])
+    box = vol.ingest(pid, fr[:0], d["poses"][:0])
+    assert _empty(box)
+    empty = Box()
+    empty.lo[:] = (5, 5, 5)
+    empty.hi[:] = (5, 9, 9)
+    V, S = vol.finalize()
+    V2, S2 = vol.finalize(empty, out=(V.clone(), S.clone()))
+    vol.sync()
+    assert torch.equal(V, V2) and torch.equal(S, S2)
+    acc = oracle.Accum(d["grid"])
+    acc.ingest(d["frames"][:20], d["poses"][:20], d["probe"])
+    assert_accum_equal(vol, acc, "after empty calls")
+
+
+def test_frames_outside_the_grid_add_nothing():
+    say("case: frames outside the grid")
+    d = synth.cfg1()
+    poses = d["poses"][:8].copy()
+    poses[:, 0, 3] += 500.0          # 500 mm to the side of a 32 mm grid
+    vol = gpu_volume(d["grid"])
+    pid = add_probe(vol, d["probe"])
+    box = vol.ingest(pid, to_dev(d["frames"][:8]), poses)
+    vol.sync()
+    assert _empty(box)
+    s, c = vol.host_accumulators()
+    assert not s.any() and not c.any()
+
+
+def test_batched_with_zero_frame_sweeps():
+    from paper_2412_00058_amd import ingest_batched
+    say("case: batched with empty sweeps")
+    cases = [synth.random_small_case(60 + i, F=6, W=48, H=40, dims=(28, 26, 30), rot_deg=45.0) for i in range(3)]
+    jobs = []
+    for i, c in enumerate(cases):
+        v = gpu_volume(c["grid"])
+        pid = add_probe(v, c["probe"])
+        fr = to_dev(c["frames"])
+        if i == 1:   # the middle sweep brings no frames
+            jobs.append((v, pid, fr[:0], c["poses"][:0]))
+        else:
+            jobs.append((v, pid, fr, c["poses"]))
+    boxes = ingest_batched(jobs)
+    assert _empty(boxes[1])
+    for i, ((v, _, _, _), c) in enumerate(zip(jobs, cases)):
+        v.sync()
+        if i == 1:
+            s, cn = v.host_accumulators()
+            assert not s.any() and not cn.any()
+        else:
+            assert_accum_equal(v, oracle_accum(c), "batched sweep %d" % i)
+
+
+def test_graph_with_convex_mask_equals_oracle():
+    from paper_2412_00058_amd import Graph
+    say("case: graph with fan mask")
+    case = synth.random_small_case(71, F=12, W=96, H=80, dims=(40, 36, 40), px=0.2, rot_deg=30.0)
+    p = case["probe"]
+    m = synth.convex_mask(p.width, p.height, p.pixel_mm[0], apex_mm=2.0, half_angle_deg=30.0)
+    case["probe"] = synth.Probe(p.width, p.height, p.pixel_mm, mask=m)
+    case["frames"] = case["frames"] * m[None]
+    vol = gpu_volume(case["grid"])
+    pid = add_probe(vol, case["probe"])
+    gr = Graph(vol, pid)
+    for n in range(case["frames"].shape[0]):
+        gr.launch(case["frames"][n], case["poses"][n])
+    vol.sync()
+    gr.close()
+    assert_accum_equal(vol, oracle_accum(case), "graph masked")
+
+
+def test_whole_spine_sweep_full_size_bit_exact():
+    """3600 frames of 480 x 640 into the 400 x 240 x 1120 grid, ingested in calls of 64 with
+    the autotuned tiling (the benchmark's configuration); accumulators, normalised volume,
+    state, depth map and slab projections equal the oracle's bit for bit."""
+    from paper_2412_00058_amd import seg_params, SEG_ALG2
+    say("case: whole-spine sweep, full size")
+    d = synth.cfg2()
+    g = d["grid"]
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    fr = to_dev(d["frames"])
+    vol.autotune(pid, fr[:512], d["poses"][:512], None)
+    say("  tile", vol.tiling(pid))
+    F = fr.shape[0]
+    for k in range(0, F, 64):
+        vol.ingest(pid, fr[k:k + 64], d["poses"][k:k + 64])
+    V, S = vol.finalize()
+    seg = dict(y_lo=40, k=6, tau_I=128, tau_G=40, r=2, fallback_y=74, half=(2, 5, 10))
+    dep, mean, mx = vol.segment_project(seg_params(mode=SEG_ALG2, **seg), V, S)
+    vol.sync()
+    del fr
+    say("  oracle")
+    acc = oracle.Accum(g)
+    for k in range(0, F, 64):
+        acc.ingest(d["frames"][k:k + 64], d["poses"][k:k + 64], d["probe"])
+    assert_accum_equal(vol, acc, "whole spine")
+    Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    do, mo, xo = oracle.segment(g, Vo, So, oracle.seg_params(mode=oracle.ALG2, **seg))
+    assert np.array_equal(dep.cpu().numpy(), do)
+    assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32))
+    assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32))
