@@ -244,3 +244,38 @@ def test_cfg1_band_ground_truth():
             good += abs(int(dep[z, x]) - want) <= 1
     assert total > 2000
     assert good >= 0.95 * total, (good, total)
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+    return rows
+
+
+def test_golden_vpi_fixed_depths():
+    """Sec. III.B fixed-depth slabs (35 / 45 mm) land on the tabulated voxel rows."""
+    for s, depth_mm, want in _golden("vpi_fixed_depths.txt"):
+        nx, ny, nz = 3, 200, 2
+        V = np.zeros((nz, ny, nx), np.uint8)
+        grid = G((nx, ny, nz), s=s)
+        d, _, _ = oracle.segment(grid, V, V, oracle.seg_params(mode=oracle.FIXED, D_mm=depth_mm, half=(2,)))
+        assert np.all(d == int(want)), (s, depth_mm, d[0, 0], want)
+
+
+def test_golden_alg1_cut_profile():
+    """Table I Step 4 at the ends, quarters and middle of a 560 mm back."""
+    rows = _golden("alg1_cut_profile.txt")
+    # z centres at (z + 1/2) 0.5 mm and z1 = 0.25 mm, so that sigma = z / 2
+    nx, ny, nz = 2, 120, 1121
+    V = np.zeros((nz, ny, nx), np.uint8)
+    for K, D, L, sigma, cut_mm, want in rows:
+        assert abs(K * abs(sigma - L / 2) + D - cut_mm) < 1e-9    # the tabulated cut itself
+        p = oracle.seg_params(mode=oracle.ALG1, K=K, D_mm=D, L_mm=L, z1_mm=0.25, half=(1,))
+        d, _, _ = oracle.segment(G((nx, ny, nz)), V, V, p)
+        z = int(round(2 * sigma))
+        assert d[z, 0] == d[z, 1] == int(want), (sigma, d[z, 0], want)
