@@ -30,15 +30,27 @@ __device__ __forceinline__ bool xcd_block(int gx, int nbands, int &bx, int &band
 }
 __host__ __forceinline__ unsigned xcd_blocks(int gx, int nbands) { return (unsigned)(8 * ((nbands + 7) / 8) * gx); }
 
+// kC columns per lane (4: one 32-bit load covers a lane's four columns of a row, which
+// needs nx % 4 == 0 and a 4-byte aligned volume; else 1).
+template <int kC>
 __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
-  __shared__ int32_t best_s_sh[kSeg][64], best_y_sh[kSeg][64];
+  __shared__ int32_t best_s_sh[kSeg][64][kC], best_y_sh[kSeg][64][kC];
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
   int bx, z;
-  if (!xcd_block((a.nx + 63) / 64, a.nz, bx, z)) return;   // uniform per block
-  const int x = bx * 64 + lane;
+  if (!xcd_block((a.nx + 64 * kC - 1) / (64 * kC), a.nz, bx, z)) return;   // uniform per block
+  const int x = (bx * 64 + lane) * kC;   // first column of this lane
   const int64_t nxy = (int64_t)a.nx * a.ny;
   const int ymax = a.ny - 1 - a.k;
-  int best = -1, best_s = 0;
+  int best[kC], best_s[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    best[c] = -1;
+    best_s[c] = 0;
+  }
+  auto row = [&](const uint8_t *col, int y) -> uint32_t {
+    if (kC == 4) return *reinterpret_cast<const uint32_t *>(col + (int64_t)y * a.nx);
+    return col[(int64_t)y * a.nx];
+  };
   if (x < a.nx && ymax >= a.y_lo) {
     const uint8_t *col = a.V + (int64_t)z * nxy + x;
     const int len = ymax - a.y_lo + 1;
@@ -46,45 +58,62 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
     const int yhi = ymax - seg * per;                  // this segment: y in [ylo, yhi]
     const int ylo = max(a.y_lo, yhi - per + 1);
     if (yhi >= ylo) {
-      int below = 0;   // sum of V(y+1 .. y+k) for y = yhi
-      for (int j = 1; j <= a.k; ++j) below += col[(int64_t)(yhi + j) * a.nx];
+      int below[kC];   // sum of V(y+1 .. y+k) for y = yhi, per column
+#pragma unroll
+      for (int c = 0; c < kC; ++c) below[c] = 0;
+      for (int j = 1; j <= a.k; ++j) {
+        const uint32_t w = row(col, yhi + j);
+#pragma unroll
+        for (int c = 0; c < kC; ++c) below[c] += (int)((w >> (8 * c)) & 0xFFu);
+      }
       const int thr = a.k * a.tau_G;
       for (int yb = yhi; yb >= ylo; yb -= kUnroll) {
-        int here[kUnroll], leave[kUnroll];
+        uint32_t here[kUnroll], leave[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int y = yb - u;
-          here[u] = y >= ylo ? col[(int64_t)y * a.nx] : 0;
-          leave[u] = y >= ylo ? col[(int64_t)(y + a.k) * a.nx] : 0;
+          here[u] = y >= ylo ? row(col, y) : 0u;
+          leave[u] = y >= ylo ? row(col, y + a.k) : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int y = yb - u;
           if (y < ylo) break;
-          const int sc = a.k * here[u] - below;
-          if (here[u] >= a.tau_I && sc >= thr && (best < 0 || sc > best_s)) {
-            best = y;
-            best_s = sc;
+#pragma unroll
+          for (int c = 0; c < kC; ++c) {
+            const int h = (int)((here[u] >> (8 * c)) & 0xFFu), l = (int)((leave[u] >> (8 * c)) & 0xFFu);
+            const int sc = a.k * h - below[c];
+            if (h >= a.tau_I && sc >= thr && (best[c] < 0 || sc > best_s[c])) {
+              best[c] = y;
+              best_s[c] = sc;
+            }
+            below[c] += h - l;
           }
-          below += here[u] - leave[u];
         }
       }
     }
   }
-  best_s_sh[seg][lane] = best_s;
-  best_y_sh[seg][lane] = best;
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    best_s_sh[seg][lane][c] = best_s[c];
+    best_y_sh[seg][lane][c] = best[c];
+  }
   __syncthreads();
-  if (seg == 0 && x < a.nx) {
+  if (seg == 0) {
     // segment 0 is the deepest; a later (shallower) segment wins only with a larger score
-    int by = best_y_sh[0][lane], bs = best_s_sh[0][lane];
-    for (int g = 1; g < kSeg; ++g) {
-      const int y = best_y_sh[g][lane], sc = best_s_sh[g][lane];
-      if (y >= 0 && (by < 0 || sc > bs)) {
-        by = y;
-        bs = sc;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) {
+      if (x + c >= a.nx) break;
+      int by = best_y_sh[0][lane][c], bs = best_s_sh[0][lane][c];
+      for (int g = 1; g < kSeg; ++g) {
+        const int y = best_y_sh[g][lane][c], sc = best_s_sh[g][lane][c];
+        if (y >= 0 && (by < 0 || sc > bs)) {
+          by = y;
+          bs = sc;
+        }
       }
+      a.raw[(int64_t)z * a.nx + x + c] = (int16_t)by;
     }
-    a.raw[(int64_t)z * a.nx + x] = (int16_t)by;
   }
 }
 
@@ -204,7 +233,10 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
 
 hipError_t launch_segment(const SegArgs &a, hipStream_t s) {
   if (a.mode == 0) {
-    hipLaunchKernelGGL(raw_depth_kernel, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), dim3(256), 0, s, a);
+    if (a.nx % 4 == 0 && (((uintptr_t)a.V) & 3u) == 0)
+      hipLaunchKernelGGL(raw_depth_kernel<4>, dim3(xcd_blocks((a.nx + 255) / 256, a.nz)), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(raw_depth_kernel<1>, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -126,3 +126,24 @@ def test_whole_spine_sweep_full_size_bit_exact():
     assert np.array_equal(dep.cpu().numpy(), do)
     assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32))
     assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32))
+
+
+def test_segment_project_odd_width_grid():
+    """A grid width that is not a multiple of 4 takes the one-column-per-lane depth scan."""
+    from paper_2412_00058_amd import seg_params, SEG_ALG1, SEG_ALG2, SEG_FIXED
+    say("case: segment on a 37-wide grid")
+    case = synth.random_small_case(81, F=24, W=120, H=100, dims=(37, 60, 30), px=0.2, rot_deg=20.0)
+    vol = gpu_volume(case["grid"])
+    pid = add_probe(vol, case["probe"])
+    vol.ingest(pid, to_dev(case["frames"]), case["poses"])
+    V, S = vol.finalize()
+    Vh, Sh = V.cpu().numpy(), S.cpu().numpy()
+    for mode, omode in ((SEG_ALG2, oracle.ALG2), (SEG_ALG1, oracle.ALG1), (SEG_FIXED, oracle.FIXED)):
+        kw = dict(y_lo=3, k=4, tau_I=100, tau_G=20, r=2, fallback_y=11, half=(1, 3), K=0.2, D_mm=4.0, L_mm=15.0,
+                  z1_mm=1.0)
+        dep, mean, mx = vol.segment_project(seg_params(mode=mode, **kw), V, S)
+        vol.sync()
+        do, mo, xo = oracle.segment(case["grid"], Vh, Sh, oracle.seg_params(mode=omode, **kw))
+        assert np.array_equal(dep.cpu().numpy(), do), mode
+        assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32)), mode
+        assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32)), mode
