@@ -89,7 +89,7 @@ def traffic_from_profile(src_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-def counters_summary(fetch_db, write_db, out_json):
+def counters_summary(fetch_db, write_db, out_json, atomic_db=None):
     """Summarise two rocprofv3 --pmc runs of `bench.py --profile-pass` (FETCH_SIZE, then
     WRITE_SIZE; rocpd sqlite output) into HBM bytes per ingest launch.  Each counter is
     scaled by what it reads for copy_u32_kernel, which the profile pass runs once on a
@@ -124,6 +124,9 @@ def counters_summary(fetch_db, write_db, out_json):
            "copy_fetch_kib": round(f_copy / 1024.0, 1), "copy_write_kib": round(w_copy / 1024.0, 1),
            "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
            "hbm_bytes_per_launch": int(f_ing * 1024.0 * kf + w_ing * 1024.0 * kw)}
+    if atomic_db:
+        atom = per_kernel(atomic_db, "TCC_EA0_ATOMIC_sum")
+        rec["atomic_requests_per_launch"] = int(atom["ingest_kernel"][0])
     for k in sorted(set(fetch) | set(write)):
         f = fetch.get(k, (0.0, 0))[0]
         w = write.get(k, (0.0, 0))[0]
@@ -253,16 +256,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the splat and batched lines")
     ap.add_argument("--profile-pass", action="store_true", help="one short pass for rocprofv3 (no oracle, no extras)")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="for rocprofv3: only the splat, graph and batched measurements (one pass each)")
     ap.add_argument("--cache", default=None,
                     help="load the generated sweep from this .npz (written there if missing); lets a profiled "
                          "run skip the generator's worker processes")
-    ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None,
-                    help="no GPU: summarise two rocprofv3 --pmc result databases of the profile pass into "
-                         "profiles/ingest_cfg2_counters.json")
+    ap.add_argument("--counters-summary", nargs="+", metavar="DB", default=None,
+                    help="no GPU: summarise the rocprofv3 --pmc result databases of the profile pass "
+                         "(FETCH_SIZE, WRITE_SIZE[, TCC_EA0_ATOMIC_sum]) into profiles/ingest_cfg2_counters.json")
     args = ap.parse_args()
     if args.counters_summary:
-        counters_summary(args.counters_summary[0], args.counters_summary[1],
-                         os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json"))
+        dbs = args.counters_summary
+        counters_summary(dbs[0], dbs[1], os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json"),
+                         dbs[2] if len(dbs) > 2 else None)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build is single-GPU only (see DESIGN.md, sharding plan)",
@@ -286,7 +292,7 @@ def main():
     # the oracle's distinct-voxel pass runs in a child forked before any GPU call
     q = None
     proc = None
-    if not args.profile_pass:
+    if not args.profile_pass and not args.extras_only:
         _SWEEP = d
         ctx = mp.get_context("fork")
         q = ctx.Queue()
@@ -297,6 +303,11 @@ def main():
     import paper_2412_00058_amd as usv
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.extras_only:
+        print(json.dumps({"extras_only": True, "fwd_bwd": bench_splat(torch, usv, 3),
+                          "graph": bench_graph(torch, usv, d, n=128, n_lat=32),
+                          "batched": bench_batched(torch, usv, 1)}))
+        return
 
     g, p = d["grid"], d["probe"]
     F = d["frames"].shape[0]
