@@ -193,14 +193,17 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
                               usv_box *dirty_out);
 
 /* Autotune the ingest tiling of a probe on sample data (n >= 1 frames) by timing
- * every candidate on a scratch copy of the grid; the winner becomes the probe's
- * tiling.  cache_path (nullable): results are read from / appended to this text
+ * every candidate tile shape on a scratch copy of the grid, then 16 and 32 frames per
+ * launch for the best shape; the winners become the probe's tiling and launch size.  cache_path (nullable): results are read from / appended to this text
  * file, keyed by device, image size, pixel/voxel ratio and mask.  Synchronous. */
 usv_status usv_autotune(usv_volume *vol, int32_t probe_id, const uint8_t *frames_dev, int64_t row_pitch,
                         int64_t frame_pitch, const double *poses_host, int32_t n, const char *cache_path);
 
 /* Tile shape used for a probe: tile width/height in pixels (for reports). */
 usv_status usv_probe_tiling(const usv_volume *vol, int32_t probe_id, int32_t *tile_w, int32_t *tile_h);
+
+/* Frames per ingest launch used for a probe (64 unless usv_autotune found fewer faster). */
+usv_status usv_probe_chunk(const usv_volume *vol, int32_t probe_id, int32_t *frames_per_launch);
 
 /* Force a probe's tile shape.  Supported shapes (w x h): 60x64, 64x48, 64x32, 32x64,
  * 32x32, 64x16, 128x8, 48x60, 40x48, 60x128, 48x120, 64x64, 32x128, 128x16, 60x96,

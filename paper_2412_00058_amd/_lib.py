@@ -16,7 +16,7 @@ EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
     "usv_ingest_frames", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
-    "usv_probe_tiling", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch", "usv_graph_destroy", "usv_splat_create",
+    "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch", "usv_graph_destroy", "usv_splat_create",
     "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss", "usv_splat_backward", "usv_fold_pose",
     "usv_dirty_box", "usv_version",
 ]
@@ -86,6 +86,7 @@ def lib():
         "usv_ingest_batched": (I32, [P, P, P, P, P, P, P, I32, P]),
         "usv_autotune": (I32, [P, I32, P, I64, I64, P, I32, C.c_char_p]),
         "usv_probe_tiling": (I32, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
+        "usv_probe_chunk": (I32, [P, I32, C.POINTER(I32)]),
         "usv_probe_set_tiling": (I32, [P, I32, I32, I32]),
         "usv_graph_create": (I32, [P, I32, PP]),
         "usv_graph_launch": (I32, [P, P, P, C.POINTER(Box)]),

@@ -40,6 +40,7 @@ struct ProbeState {
   uint8_t *d_tile_class = nullptr;
   uint8_t *d_tile_class_safe = nullptr;
   Tiling t{};        // tiling of ordinary frames
+  int chunk = kLaunchFrames;   // frames per ingest launch (autotuned, <= kLaunchFrames)
   Tiling t_safe{};   // <= 4095-pixel tiling, for frames that put > 2056 pixels in one voxel
   double mask_density = 1.0;
 };
@@ -395,8 +396,9 @@ usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *fram
   IngestLaunch a{};
   a.d = make_desc(v, p, frames, row_pitch, frame_pitch, safe);
   const int per_frame = a.d.t.tiles_x * a.d.t.tiles_y;
-  for (int f0 = 0; f0 < nk; f0 += kLaunchFrames) {
-    const int cnt = std::min(kLaunchFrames, nk - f0);
+  const int chunk = std::max(1, std::min(p.chunk, kLaunchFrames));
+  for (int f0 = 0; f0 < nk; f0 += chunk) {
+    const int cnt = std::min(chunk, nk - f0);
     a.n_frames = cnt;
     for (int i = 0; i < cnt; ++i) {
       a.fidx[i] = fidx[f0 + i];
@@ -700,6 +702,12 @@ usv_status usv_probe_tiling(const usv_volume *v, int32_t probe_id, int32_t *tile
   return USV_OK;
 }
 
+usv_status usv_probe_chunk(const usv_volume *v, int32_t probe_id, int32_t *frames_per_launch) {
+  if (!v || probe_id < 0 || probe_id >= (int32_t)v->probes.size() || !frames_per_launch) return USV_E_ARG;
+  *frames_per_launch = v->probes[(size_t)probe_id].chunk;
+  return USV_OK;
+}
+
 usv_status usv_probe_set_tiling(usv_volume *v, int32_t probe_id, int32_t tile_w, int32_t tile_h) {
   if (!v || probe_id < 0 || probe_id >= (int32_t)v->probes.size()) return fail(v, USV_E_ARG, "unknown probe");
   ProbeState &p = v->probes[(size_t)probe_id];
@@ -927,11 +935,14 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
     while (std::getline(in, line)) {
       std::istringstream ss(line);
       std::string k;
-      int lr = 0, kr = 0;
+      int lr = 0, kr = 0, chunk = kLaunchFrames;
       if (ss >> k >> lr >> kr && k == key) {
+        float ms = 0.0f;
+        if (!(ss >> chunk >> ms) || chunk < 1 || chunk > kLaunchFrames) chunk = kLaunchFrames;
         Tiling t = make_tiling(lr, kr, p.W, p.H);
         if (!tiling_valid(t)) break;
         p.t = t;
+        p.chunk = chunk;
         return check_hip(v, upload_tile_class(p), "tile classes");
       }
     }
@@ -964,22 +975,23 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   const Tiling keep = p.t;
   Tiling best = keep;
   float best_ms = 1e30f;
-  for (const TileCand &c : kCands) {
-    Tiling t = make_tiling(c.lr, c.kr, p.W, p.H);
-    if (!tiling_valid(t)) continue;
+  int best_chunk = kLaunchFrames;
+  // time one (tile shape, frames per launch) setting on the scratch grid; < 0 if unusable
+  auto trial = [&](const Tiling &t, int chunk) -> float {
     p.t = t;
-    if (upload_tile_class(p) != hipSuccess) continue;
+    p.chunk = chunk;
+    if (upload_tile_class(p) != hipSuccess) return -1.0f;
     // the frame split depends on the candidate's LDS packing
     std::vector<float> maps, smaps;
     std::vector<int32_t> fidx, sfidx;
-    if (prepare_frames(v, p, poses, n, maps, fidx, nullptr, &smaps, &sfidx) != USV_OK) break;
+    if (prepare_frames(v, p, poses, n, maps, fidx, nullptr, &smaps, &sfidx) != USV_OK) return -1.0f;
     auto run = [&]() {
       usv_status r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);
       if (r == USV_OK && !sfidx.empty()) r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
       return r;
     };
     (void)launch_zero_u32((uint32_t *)scratch, (int64_t)(bytes / 4), v->stream);
-    if (run() != USV_OK) continue;   // warm-up
+    if (run() != USV_OK) return -1.0f;   // warm-up
     float ms_best = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
       (void)hipEventRecord(e0, v->stream);
@@ -990,9 +1002,23 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
       (void)hipEventElapsedTime(&ms, e0, e1);
       ms_best = std::min(ms_best, ms);
     }
-    if (ms_best < best_ms) {
-      best_ms = ms_best;
+    return ms_best;
+  };
+  // every tile shape with full launches, then fewer frames per launch for the best shape
+  for (const TileCand &c : kCands) {
+    const Tiling t = make_tiling(c.lr, c.kr, p.W, p.H);
+    if (!tiling_valid(t)) continue;
+    const float ms = trial(t, kLaunchFrames);
+    if (ms >= 0.0f && ms < best_ms) {
+      best_ms = ms;
       best = t;
+    }
+  }
+  for (int ch : {16, 32}) {
+    const float ms = trial(best, ch);
+    if (ms >= 0.0f && ms < best_ms) {
+      best_ms = ms;
+      best_chunk = ch;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1001,11 +1027,12 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   (void)hipFree(scratch);
   (void)hipFree(err);
   p.t = best;
+  p.chunk = best_chunk;
   st = check_hip(v, upload_tile_class(p), "tile classes");
   if (st != USV_OK) return st;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    if (out) out << key << " " << best.lr << " " << best.kr << " " << best_ms << "\n";
+    if (out) out << key << " " << best.lr << " " << best.kr << " " << best_chunk << " " << best_ms << "\n";
   }
   return USV_OK;
 }

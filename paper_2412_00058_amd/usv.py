@@ -123,6 +123,12 @@ class Volume:
         check(lib().usv_probe_tiling(self.h, probe_id, C.byref(w), C.byref(h)), self.h)
         return w.value, h.value
 
+    def chunk(self, probe_id: int) -> int:
+        """Frames per ingest launch for this probe (set by autotune; 64 by default)."""
+        n = C.c_int32()
+        check(lib().usv_probe_chunk(self.h, probe_id, C.byref(n)), self.h)
+        return n.value
+
     def set_tiling(self, probe_id, tile_w, tile_h):
         check(lib().usv_probe_set_tiling(self.h, probe_id, int(tile_w), int(tile_h)), self.h)
 
