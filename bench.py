@@ -13,7 +13,8 @@ oracle) divided by the launch duration measured with HIP events on the library's
 `cpu_baseline` times the CPU oracle on the same step on one host core.
 Beside the main line: differentiable splat forward+backward frames/s (512 frames of
 320 x 240 into 256 x 192 x 512), single-frame captured-graph ingest from host memory
-(frames/s back to back, p50/p99 latency) and batched 16-sweep ingest frames/s.
+(frames/s back to back, p50/p99 latency), the real-time pipeline (every frame pushed,
+region finalize + depth/projection every 10 frames) and batched 16-sweep ingest frames/s.
 """
 from __future__ import annotations
 
@@ -213,6 +214,44 @@ def bench_graph(torch, usv, d, n=512, n_lat=200):
         raise RuntimeError("graph ingest reported an error")
     lat = np.sort(np.array(lat)) * 1e3
     return rate, float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def bench_realtime(torch, usv, d, render_every=10, n_upd=30):
+    """Real-time incremental imaging: every whole-spine frame pushed from host memory
+    through the pipeline (captured-graph ingest), the touched region finalized and the
+    depth map + projections recomputed every `render_every` frames.  Returns (sustained
+    frames/s over the sweep including renders, median ms of one display update = push of
+    `render_every` frames + render + completion)."""
+    g, p = d["grid"], d["probe"]
+    vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+    pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+    pl = usv.Pipeline(vol, pid, usv.seg_params(mode=usv.SEG_ALG2, **SEG), render_every)
+    L = usv.lib()
+    F = d["frames"].shape[0]
+    fr = d["frames"]
+    P = np.ascontiguousarray(d["poses"].reshape(F, 16))
+    fp = [C.c_void_p(fr[i].ctypes.data) for i in range(F)]
+    pp = [C.c_void_p(P[i].ctypes.data) for i in range(F)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(F):
+        if L.usv_pipeline_push(pl.h, fp[i], pp[i]) != 0:
+            raise RuntimeError("pipeline push failed")
+    if L.usv_pipeline_flush(pl.h) != 0:
+        raise RuntimeError("pipeline flush failed")
+    rate = F / (time.perf_counter() - t0)
+    upd = []
+    for k in range(n_upd):
+        t = time.perf_counter()
+        for j in range(render_every):
+            i = (k * render_every + j) % F
+            L.usv_pipeline_push(pl.h, fp[i], pp[i])
+        L.usv_pipeline_flush(pl.h)
+        upd.append(time.perf_counter() - t)
+    pl.close()
+    if vol.status() != 0:
+        raise RuntimeError("pipeline reported an error")
+    return rate, float(np.median(upd)) * 1e3
 
 
 def bench_batched(torch, usv, steps):
@@ -427,6 +466,12 @@ def main():
             extras["graph_latency_ms_p99"] = round(p99, 4)
         except Exception as e:
             extras["graph_error"] = repr(e)
+        try:
+            rate, upd = bench_realtime(torch, usv, d)
+            extras["realtime_frames_per_s"] = round(rate, 1)
+            extras["realtime_update_ms_p50"] = round(upd, 3)
+        except Exception as e:
+            extras["realtime_error"] = repr(e)
         try:
             fps, ms, tot = bench_batched(torch, usv, max(2, min(args.steps, 5)))
             extras["batched_frames_per_s"] = round(fps, 1)

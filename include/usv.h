@@ -224,6 +224,30 @@ usv_status usv_graph_launch(usv_graph *g, const uint8_t *frame_host, const doubl
 usv_status usv_graph_destroy(usv_graph *g);
 
 /* ---------------------------------------------------------------------------------
+ * Real-time incremental imaging (Sec. II.C: only newly acquired frames are
+ * reconstructed and only the updated region is rendered, at the frame rate).
+ * usv_pipeline_create: the caller's output buffers (device memory, caller-owned, sized
+ * for the volume's grid: vol_u8 and state nz*ny*nx, depth nz*nx int16, mean and max
+ * params->n_half*nz*nx FP32) are first filled from the accumulators as they are
+ * (full finalize + segment_project).  usv_pipeline_push: one frame (host memory, row
+ * pitch = width) and its 16-double pose, compounded through a captured graph of the
+ * probe (usv_graph_*); after every render_every pushed frames the union of their dirty
+ * boxes is finalized (region form) and the depth map and projections recomputed.
+ * usv_pipeline_flush renders what is pending and waits for the stream (usv_sync
+ * semantics); after it the outputs equal usv_finalize(NULL) + usv_segment_project.
+ * Everything is ordered on the volume's stream.  Errors: USV_E_ARG for bad arguments
+ * (render_every >= 1), otherwise those of the calls above. */
+typedef struct usv_pipeline usv_pipeline;
+usv_status usv_pipeline_create(usv_volume *vol, int32_t probe_id, const usv_seg_params *params, int32_t render_every,
+                               uint8_t *vol_u8_dev, uint8_t *state_dev, int16_t *depth_dev, float *mean_dev,
+                               float *max_dev, usv_pipeline **out);
+usv_status usv_pipeline_push(usv_pipeline *pl, const uint8_t *frame_host, const double *pose_host);
+usv_status usv_pipeline_flush(usv_pipeline *pl);
+/* frames pushed and renders done so far */
+usv_status usv_pipeline_stats(const usv_pipeline *pl, int64_t *frames, int64_t *renders);
+usv_status usv_pipeline_destroy(usv_pipeline *pl);
+
+/* ---------------------------------------------------------------------------------
  * Differentiable trilinear splat (not in the paper; pose refinement against patient
  * motion, cf. Sec. III.A).  Frame n uses T_n = Exp(xi_n) T*_n with xi = (rho [mm],
  * omega [rad]) a left se(3) perturbation of the image->world pose T*_n (FP64 4x4).

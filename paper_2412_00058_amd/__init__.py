@@ -3,6 +3,6 @@ scatter, normalise + hole fill, bone-depth segmentation and slab projection, plu
 differentiable trilinear splat), implemented as HIP kernels for gfx950 behind the C ABI
 in include/usv.h.  This package is the thin Python binding of that library."""
 from ._lib import LIB_PATH, Box, UsvError, lib  # noqa: F401
-from .usv import (EMPTY, FILLED, MEASURED, SEG_ALG1, SEG_ALG2, SEG_FIXED, Graph, OverlapLossFn,  # noqa: F401
+from .usv import (EMPTY, FILLED, MEASURED, SEG_ALG1, SEG_ALG2, SEG_FIXED, Graph, OverlapLossFn, Pipeline,  # noqa: F401
                   SplatContext, SplatFn, Volume, accumulator_bytes, dirty_box, fold_pose, ingest_batched,
                   seg_params, version)

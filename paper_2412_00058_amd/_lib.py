@@ -16,9 +16,10 @@ EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
     "usv_ingest_frames", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
-    "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch", "usv_graph_destroy", "usv_splat_create",
-    "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss", "usv_splat_backward", "usv_fold_pose",
-    "usv_dirty_box", "usv_version",
+    "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
+    "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
+    "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
+    "usv_splat_backward", "usv_fold_pose", "usv_dirty_box", "usv_version",
 ]
 
 
@@ -91,6 +92,11 @@ def lib():
         "usv_graph_create": (I32, [P, I32, PP]),
         "usv_graph_launch": (I32, [P, P, P, C.POINTER(Box)]),
         "usv_graph_destroy": (I32, [P]),
+        "usv_pipeline_create": (I32, [P, I32, P, I32, P, P, P, P, P, PP]),
+        "usv_pipeline_push": (I32, [P, P, P]),
+        "usv_pipeline_flush": (I32, [P]),
+        "usv_pipeline_stats": (I32, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "usv_pipeline_destroy": (I32, [P]),
         "usv_splat_create": (I32, [C.POINTER(GridDesc), I32, I32, D, D, I32, P, PP]),
         "usv_splat_destroy": (I32, [P]),
         "usv_splat_forward": (I32, [P, P, P, P, I32, P]),

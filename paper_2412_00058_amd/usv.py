@@ -245,6 +245,53 @@ class Graph:
             pass
 
 
+class Pipeline:
+    """Real-time incremental imaging: frames pushed one at a time (host memory) through a
+    captured graph; every `render_every` frames the touched region is finalized and the
+    depth map + projections recomputed into this object's device tensors."""
+
+    def __init__(self, vol: Volume, probe_id: int, params: SegParams, render_every: int = 10):
+        nx, ny, nz = vol.dims
+        dev = vol.acc.device
+        self.V = torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev)
+        self.S = torch.empty_like(self.V)
+        self.depth = torch.empty((nz, nx), dtype=torch.int16, device=dev)
+        self.mean = torch.empty((params.n_half, nz, nx), dtype=torch.float32, device=dev)
+        self.max = torch.empty_like(self.mean)
+        self.params = params
+        h = C.c_void_p()
+        check(lib().usv_pipeline_create(vol.h, probe_id, C.byref(params), int(render_every), _vp(self.V), _vp(self.S),
+                                        _vp(self.depth), _vp(self.mean), _vp(self.max), C.byref(h)), vol.h)
+        self.h = h
+        self.vol = vol
+
+    def push(self, frame_host: np.ndarray, pose):
+        f = np.ascontiguousarray(frame_host, dtype=np.uint8)
+        P = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+        check(lib().usv_pipeline_push(self.h, f.ctypes.data_as(C.c_void_p), P.ctypes.data_as(C.c_void_p)),
+              self.vol.h)
+
+    def flush(self):
+        check(lib().usv_pipeline_flush(self.h), self.vol.h)
+        return self.V, self.S, self.depth, self.mean, self.max
+
+    def stats(self):
+        f, r = C.c_int64(), C.c_int64()
+        check(lib().usv_pipeline_stats(self.h, C.byref(f), C.byref(r)))
+        return f.value, r.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().usv_pipeline_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # --- host-only helpers ------------------------------------------------------------------
 
 

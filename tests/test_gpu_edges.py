@@ -147,3 +147,32 @@ def test_segment_project_odd_width_grid():
         assert np.array_equal(dep.cpu().numpy(), do), mode
         assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32)), mode
         assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32)), mode
+
+
+def test_realtime_pipeline_equals_full_path():
+    """Frames pushed one at a time with renders every 7 frames: after each flush the
+    outputs equal a full finalize + segment_project of the frames so far (oracle)."""
+    from paper_2412_00058_amd import Pipeline, seg_params, SEG_ALG2
+    say("case: real-time pipeline")
+    d = synth.cfg1()
+    g = d["grid"]
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    kw = dict(y_lo=0, k=6, tau_I=128, tau_G=40, r=2, fallback_y=20, half=(2, 5, 10))
+    pl = Pipeline(vol, pid, seg_params(mode=SEG_ALG2, **kw), render_every=7)
+    for stop in (30, 64):
+        start = 0 if stop == 30 else 30
+        for n in range(start, stop):
+            pl.push(d["frames"][n], d["poses"][n])
+        V, S, dep, mean, mx = pl.flush()
+        acc = oracle.Accum(g)
+        acc.ingest(d["frames"][:stop], d["poses"][:stop], d["probe"])
+        Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+        assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So), stop
+        do, mo, xo = oracle.segment(g, Vo, So, oracle.seg_params(mode=oracle.ALG2, **kw))
+        assert np.array_equal(dep.cpu().numpy(), do), stop
+        assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32)), stop
+        assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32)), stop
+    frames, renders = pl.stats()
+    assert frames == 64 and renders >= 64 // 7
+    pl.close()
