@@ -179,6 +179,38 @@ def bench_splat(torch, usv, steps):
     return F / dt, dt * 1e3
 
 
+def bench_refine(torch, usv, iters=150):
+    """Rigid-motion refinement at 256 frames of 320 x 240 (two interleaved passes with a
+    1.1 mm / 1.1 deg patient motion between them): ms per device-side Adam step (forward
+    splat, loss, pose-only backward, update) and the residual motion after `iters` steps,
+    measured with the matrix exponential of the twist (scipy), not the library."""
+    import math
+    import scipy.linalg
+    import synth
+    d = synth.two_pass_case()
+    g, p = d["grid"], d["probe"]
+    F = d["I"].shape[0]
+    ctx = usv.SplatContext(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, F)
+    I = torch.from_numpy(d["I"]).cuda()
+    T = torch.from_numpy(d["Tstar"]).cuda()
+    kw = dict(iters=iters, lr_rho=0.1, lr_omega=math.radians(0.1))
+    ctx.refine_motion(I, T, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xi, L = ctx.refine_motion(I, T, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    x = xi.cpu().numpy()
+    hat = np.zeros((4, 4))
+    hat[:3, 3] = x[:3]
+    hat[:3, :3] = [[0, -x[5], x[4]], [x[5], 0, -x[3]], [-x[4], x[3], 0]]
+    E = scipy.linalg.expm(hat) @ np.linalg.inv(d["delta"])
+    ang = math.degrees(math.acos(min(1.0, (np.trace(E[:3, :3]) - 1.0) / 2.0)))
+    Lh = L.cpu().numpy()
+    return dt * 1e3 / iters, float(np.linalg.norm(E[:3, 3])), ang, float(Lh[-1] / Lh[0])
+
+
 def bench_graph(torch, usv, d, n=512, n_lat=200):
     """Real-time path: one frame per captured-graph launch from host memory (pinned
     staging copy, H2D, ingest).  Returns (frames/s back to back, p50 and p99 latency in
@@ -345,6 +377,7 @@ def main():
     if args.extras_only:
         print(json.dumps({"extras_only": True, "fwd_bwd": bench_splat(torch, usv, 3),
                           "graph": bench_graph(torch, usv, d, n=128, n_lat=32),
+                          "refine": bench_refine(torch, usv, 20),
                           "batched": bench_batched(torch, usv, 1)}))
         return
 
@@ -459,6 +492,14 @@ def main():
             extras["fwd_bwd_ms_per_step"] = round(ms, 3)
         except Exception as e:  # report, do not hide
             extras["fwd_bwd_error"] = repr(e)
+        try:
+            ms, rt, ra, drop = bench_refine(torch, usv)
+            extras["refine_ms_per_iter"] = round(ms, 4)
+            extras["refine_residual_mm"] = round(rt, 5)
+            extras["refine_residual_deg"] = round(ra, 5)
+            extras["refine_loss_ratio"] = float("%.3g" % drop)
+        except Exception as e:
+            extras["refine_error"] = repr(e)
         try:
             rate, p50, p99 = bench_graph(torch, usv, d)
             extras["graph_frames_per_s"] = round(rate, 1)

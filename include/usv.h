@@ -272,11 +272,35 @@ usv_status usv_splat_forward(usv_splat *ctx, const float *I_dev, const double *T
 usv_status usv_overlap_loss(usv_splat *ctx, const float *vols_dev, double *loss_dev, float *grads_dev);
 
 /* Backward of any loss through the splat given grads_dev = dL/d(S_A, W_A, S_B, W_B)
- * (FP32 [4][nvox]): dI_dev [F][H][W] FP32 receives dL/dI and dxi_dev [F][6] FP64
+ * (FP32 [4][nvox]): dI_dev [F][H][W] FP32 (nullable) receives dL/dI and dxi_dev [F][6] FP64
  * receives dL/dxi = J_l(xi)^T (sum dL/dx, sum x cross dL/dx), with x the pixel's
  * world point and J_l the SE(3) left Jacobian.  Weights are recomputed, not stored. */
 usv_status usv_splat_backward(usv_splat *ctx, const float *I_dev, const double *Tstar_dev, const double *xi_dev,
                               int32_t F, const float *grads_dev, float *dI_dev, double *dxi_dev);
+
+/* Rigid patient motion between the two frame sets (motivated by Sec. III.A: the
+ * patient moves between sweeps, so one sweep's tracked poses are off by one rigid
+ * transform).  The odd frames are taken to be seen after a motion: their poses are
+ * T_n = Exp(xi) T*_n with one shared xi, the even frames keep T*_n.  Adam (Kingma and
+ * Ba, 2015) on xi minimises the overlap loss above: per step one forward splat, loss,
+ * backward (pose gradient only; dL/dxi = sum over odd n of dL/dxi_n) and a device-side
+ * update, all on the context's stream with no host synchronisation.
+ *   xi_dev    : 6 FP64 (rho mm, omega rad); read as the start, overwritten with the result
+ *   loss_dev  : iters + 1 FP64; loss_dev[t] is the loss before step t + 1, the last
+ *               entry the loss at the returned xi
+ *   vols_dev, grads_dev : FP32 [4][nvox] workspaces (vols_dev ends with the volumes at
+ *               the returned xi)
+ * Errors: USV_E_ARG for F outside [1, max_frames], null pointers, iters < 0, negative or
+ * non-finite step sizes, betas outside [0, 1) or eps <= 0. */
+typedef struct usv_refine_params {
+  int32_t iters;     /* Adam steps */
+  double lr_rho;     /* step size of the translation, mm */
+  double lr_omega;   /* step size of the rotation, rad */
+  double beta1, beta2, eps;
+} usv_refine_params;
+usv_status usv_refine_motion(usv_splat *ctx, const float *I_dev, const double *Tstar_dev, int32_t F,
+                             const usv_refine_params *params, double *xi_dev, double *loss_dev, float *vols_dev,
+                             float *grads_dev);
 
 /* ---------------------------------------------------------------------------------
  * Host-only helpers (no device work; usable without a GPU)

@@ -215,3 +215,42 @@ def splat_backward(grid, I, Tstar, xi, probe, grads):
                              float(probe.pixel_mm[0]), float(probe.pixel_mm[1]), *[_p(x) for x in g],
                              _p(dI), _p(dxi))
     return dI, dxi
+
+
+# --- rigid-motion refinement ----------------------------------------------------------------
+
+
+def adam_step(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, 2015, Algorithm 1) of parameters x with gradient g
+    at step t >= 1; lr may be per component.  Returns (x, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return x - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def refine_motion(grid, I, Tstar, probe, xi0=None, iters=150, lr_rho=0.05, lr_omega=np.radians(0.05), beta1=0.9,
+                  beta2=0.999, eps=1e-8):
+    """Motion between the two frame sets (Sec. III.A: the patient moves between sweeps):
+    odd frames posed at Exp(xi) T*_n with one shared xi, even frames at T*_n.  Adam on xi
+    over the overlap loss, whose gradient is the sum of the odd frames' pose gradients.
+    Returns (xi [6], losses [iters + 1]); losses[t] is the loss before step t + 1."""
+    F = I.shape[0]
+    xi = np.zeros(6) if xi0 is None else np.array(xi0, dtype=np.float64)
+    m = np.zeros(6)
+    v = np.zeros(6)
+    lr = np.array([lr_rho] * 3 + [lr_omega] * 3)
+    odd = (np.arange(F) % 2 == 1)[:, None]
+    losses = []
+    for t in range(1, iters + 2):
+        xif = np.where(odd, xi[None, :], 0.0)
+        vols = splat_forward(grid, I, Tstar, xif, probe)
+        if t == iters + 1:
+            losses.append(overlap_loss(vols, want_grads=False))
+            break
+        L, G = overlap_loss(vols)
+        losses.append(L)
+        _, dxi = splat_backward(grid, I, Tstar, xif, probe, G)
+        xi, m, v = adam_step(xi, dxi[1::2].sum(axis=0), m, v, t, lr, beta1, beta2, eps)
+    return xi, np.array(losses)

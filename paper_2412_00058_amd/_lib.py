@@ -19,7 +19,7 @@ EXPORTS = [
     "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
     "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
-    "usv_splat_backward", "usv_fold_pose", "usv_dirty_box", "usv_version",
+    "usv_splat_backward", "usv_refine_motion", "usv_fold_pose", "usv_dirty_box", "usv_version",
 ]
 
 
@@ -49,6 +49,11 @@ class SegParams(C.Structure):
                 ("tau_G", C.c_int32), ("r", C.c_int32), ("fallback_y", C.c_int32), ("n_half", C.c_int32),
                 ("half", C.c_int32 * 4), ("K", C.c_double), ("D_mm", C.c_double), ("L_mm", C.c_double),
                 ("z1_mm", C.c_double), ("yref_mm", C.c_double)]
+
+
+class RefineParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("lr_rho", C.c_double), ("lr_omega", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
 
 
 class UsvError(RuntimeError):
@@ -102,6 +107,7 @@ def lib():
         "usv_splat_forward": (I32, [P, P, P, P, I32, P]),
         "usv_overlap_loss": (I32, [P, P, P, P]),
         "usv_splat_backward": (I32, [P, P, P, P, I32, P, P, P]),
+        "usv_refine_motion": (I32, [P, P, P, I32, C.POINTER(RefineParams), P, P, P, P]),
         "usv_fold_pose": (I32, [C.POINTER(GridDesc), C.POINTER(ProbeDesc), P, P]),
         "usv_dirty_box": (I32, [C.POINTER(GridDesc), C.POINTER(ProbeDesc), P, I32, C.POINTER(Box)]),
         "usv_version": (C.c_char_p, []),

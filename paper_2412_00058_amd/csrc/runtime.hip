@@ -105,6 +105,9 @@ struct usv_splat {
   double *d_partial = nullptr;
   int n_loss_partial = 1024;
   double *d_loss_partial = nullptr;
+  double *d_xif = nullptr;     // per-frame perturbations of the motion refinement [max_frames][6]
+  double *d_dxi = nullptr;     // per-frame pose gradients [max_frames][6]
+  double *d_state = nullptr;   // refinement state: xi[6], Adam m[6], v[6]
 };
 
 namespace {
@@ -1160,7 +1163,10 @@ usv_status usv_splat_create(const usv_grid_desc *grid, int32_t W, int32_t H, dou
   if (hipMalloc(&c->d_Mq, sizeof(double) * 9 * max_frames) != hipSuccess ||
       hipMalloc(&c->d_Jt, sizeof(double) * 36 * max_frames) != hipSuccess ||
       hipMalloc(&c->d_partial, sizeof(double) * 6 * tiles * max_frames) != hipSuccess ||
-      hipMalloc(&c->d_loss_partial, sizeof(double) * c->n_loss_partial) != hipSuccess) {
+      hipMalloc(&c->d_loss_partial, sizeof(double) * c->n_loss_partial) != hipSuccess ||
+      hipMalloc(&c->d_xif, sizeof(double) * 6 * max_frames) != hipSuccess ||
+      hipMalloc(&c->d_dxi, sizeof(double) * 6 * max_frames) != hipSuccess ||
+      hipMalloc(&c->d_state, sizeof(double) * 18) != hipSuccess) {
     usv_splat_destroy(c);
     return USV_E_OOM;
   }
@@ -1175,6 +1181,9 @@ usv_status usv_splat_destroy(usv_splat *c) {
   if (c->d_Jt) (void)hipFree(c->d_Jt);
   if (c->d_partial) (void)hipFree(c->d_partial);
   if (c->d_loss_partial) (void)hipFree(c->d_loss_partial);
+  if (c->d_xif) (void)hipFree(c->d_xif);
+  if (c->d_dxi) (void)hipFree(c->d_dxi);
+  if (c->d_state) (void)hipFree(c->d_state);
   delete c;
   return USV_OK;
 }
@@ -1195,9 +1204,38 @@ usv_status usv_overlap_loss(usv_splat *c, const float *vols, double *loss, float
 
 usv_status usv_splat_backward(usv_splat *c, const float *I, const double *Tstar, const double *xi, int32_t F,
                               const float *grads, float *dI, double *dxi) {
-  if (!c || F < 0 || F > c->max_frames || !grads || (F > 0 && (!I || !Tstar || !xi || !dI || !dxi))) return USV_E_ARG;
+  if (!c || F < 0 || F > c->max_frames || !grads || (F > 0 && (!I || !Tstar || !xi || !dxi))) return USV_E_ARG;
   if (launch_splat_pose(c->g, Tstar, xi, F, c->d_Mq, c->d_Jt, c->stream) != hipSuccess) return USV_E_DEVICE;
   if (launch_splat_backward(c->g, I, c->d_Mq, c->d_Jt, F, grads, dI, c->d_partial, dxi, c->stream) != hipSuccess)
+    return USV_E_DEVICE;
+  return USV_OK;
+}
+
+usv_status usv_refine_motion(usv_splat *c, const float *I, const double *Tstar, int32_t F, const usv_refine_params *p,
+                             double *xi, double *loss, float *vols, float *grads) {
+  if (!c || !p || F < 1 || F > c->max_frames || !I || !Tstar || !xi || !loss || !vols || !grads) return USV_E_ARG;
+  if (p->iters < 0 || !(p->lr_rho >= 0.0) || !(p->lr_omega >= 0.0) || !std::isfinite(p->lr_rho) ||
+      !std::isfinite(p->lr_omega) || !(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
+      !(p->eps > 0.0) || !std::isfinite(p->eps))
+    return USV_E_ARG;
+  const RefineAdam a{p->lr_rho, p->lr_omega, p->beta1, p->beta2, p->eps};
+  hipStream_t s = c->stream;
+  if (hipMemcpyAsync(c->d_state, xi, sizeof(double) * 6, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      launch_refine_step(c->d_dxi, F, 0, a, c->d_state, c->d_xif, s) != hipSuccess)
+    return USV_E_DEVICE;
+  for (int t = 1; t <= p->iters + 1; ++t) {
+    const bool last = t == p->iters + 1;   // the loss at the final motion, no step
+    if (launch_splat_pose(c->g, Tstar, c->d_xif, F, c->d_Mq, c->d_Jt, s) != hipSuccess ||
+        launch_splat_forward(c->g, I, c->d_Mq, F, vols, s) != hipSuccess ||
+        launch_overlap_loss(c->nvox, vols, last ? nullptr : grads, c->d_loss_partial, c->n_loss_partial, loss + t - 1,
+                            s) != hipSuccess)
+      return USV_E_DEVICE;
+    if (last) break;
+    if (launch_splat_backward(c->g, I, c->d_Mq, c->d_Jt, F, grads, nullptr, c->d_partial, c->d_dxi, s) != hipSuccess ||
+        launch_refine_step(c->d_dxi, F, t, a, c->d_state, c->d_xif, s) != hipSuccess)
+      return USV_E_DEVICE;
+  }
+  if (hipMemcpyAsync(xi, c->d_state, sizeof(double) * 6, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return USV_E_DEVICE;
   return USV_OK;
 }

@@ -13,7 +13,8 @@
 //                          dL/dI and a per-tile FP64 partial of (sum dL/dq, sum (p - p_c)
 //                          x dL/dq);
 //   frame_reduce_kernel  : per frame, sums the tile partials in tile order (deterministic)
-//                          and applies J_l^T.
+//                          and applies J_l^T;
+//   refine_step_kernel   : one Adam step on a rigid motion shared by the odd frames.
 #include "usv_internal.h"
 
 namespace usv {
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restr
 // Backward of one 32x32 pixel tile.  The tile's voxel window of the frame set's two
 // gradient volumes (dL/dS, dL/dW) is staged in LDS with coalesced row loads, so the 8
 // corner gathers of each pixel are LDS reads; windows too large for LDS gather from
-// global memory.
+// global memory.  dI may be null (pose gradient only).
 __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float *__restrict__ I,
                                                         const double *__restrict__ Mq, const float *__restrict__ grads,
                                                         float *__restrict__ dI, double *__restrict__ partial) {
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
       gq[1] += coef * (by ? 1.0f : -1.0f) * fx * fz;
       gq[2] += coef * (bz ? 1.0f : -1.0f) * fx * fy;
     }
-    dI[pix] = di;
+    if (dI) dI[pix] = di;
     const float rx = (float)(pd[0] - pc[0]), ry = (float)(pd[1] - pc[1]), rz = (float)(pd[2] - pc[2]);
     acc[0] += gq[0];
     acc[1] += gq[1];
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
     acc[5] += rx * gq[1] - ry * gq[0];
   }
   // pixels of a tile outside the grid still get dL/dI = 0
-  if (!any) {
+  if (!any && dI) {
     for (int ty = ty0; ty < STH; ty += 8) {
       const int v = v0 + ty;
       if (u <= u1 && v <= v1) dI[((int64_t)f * g.H + v) * g.W + u] = 0.0f;
@@ -422,6 +423,44 @@ __global__ void frame_reduce_kernel(SplatGeom g, const double *__restrict__ Mq, 
   }
 }
 
+// One Adam step on the shared motion xi of the odd frames (the moving frame set): the
+// motion gradient is the sum of the per-frame gradients dL/dxi_n over odd n (each odd
+// frame's pose is Exp(xi) T*_n, so d xi_n / d xi = identity), summed in frame order.
+// Adam (Kingma and Ba, 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// xi -= lr m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps), lr per component (translation in mm,
+// rotation in rad).  t = 0 only initialises m, v = 0.  Then every frame's perturbation
+// is rewritten: xi for odd frames, 0 for even frames.  One block of 64 threads.
+__global__ void refine_step_kernel(const double *__restrict__ dxi, int F, int t, RefineAdam a,
+                                   double *__restrict__ state, double *__restrict__ xi_frames) {
+  // state: xi[6], m[6], v[6]
+  __shared__ double xs[6];
+  const int k = threadIdx.x;
+  if (k < 6) {
+    double x = state[k];
+    if (t == 0) {
+      state[6 + k] = 0.0;
+      state[12 + k] = 0.0;
+    } else {
+      double gsum = 0.0;
+      for (int n = 1; n < F; n += 2) gsum += dxi[6 * n + k];
+      const double m = a.beta1 * state[6 + k] + (1.0 - a.beta1) * gsum;
+      const double v = a.beta2 * state[12 + k] + (1.0 - a.beta2) * gsum * gsum;
+      state[6 + k] = m;
+      state[12 + k] = v;
+      const double mh = m / (1.0 - pow(a.beta1, (double)t));
+      const double vh = v / (1.0 - pow(a.beta2, (double)t));
+      x -= (k < 3 ? a.lr_rho : a.lr_omega) * mh / (sqrt(vh) + a.eps);
+      state[k] = x;
+    }
+    xs[k] = x;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 6 * F; e += 64) {
+    const int n = e / 6;
+    xi_frames[e] = (n & 1) ? xs[e - 6 * n] : 0.0;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_splat_pose(const SplatGeom &g, const double *Tstar, const double *xi, int F, double *Mq, double *Jt,
@@ -458,6 +497,12 @@ hipError_t launch_splat_backward(const SplatGeom &g, const float *I, const doubl
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(frame_reduce_kernel, dim3((F + 63) / 64), dim3(64), 0, s, g, Mq, Jt, partial, F, dxi);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_step(const double *dxi, int F, int t, const RefineAdam &a, double *state, double *xi_frames,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(refine_step_kernel, dim3(1), dim3(64), 0, s, dxi, F, t, a, state, xi_frames);
   return hipGetLastError();
 }
 

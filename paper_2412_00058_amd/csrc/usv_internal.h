@@ -136,4 +136,11 @@ hipError_t launch_overlap_loss(int64_t nvox, const float *vols, float *grads, do
 hipError_t launch_splat_backward(const SplatGeom &g, const float *I, const double *Mq, const double *Jt, int F,
                                  const float *grads, float *dI, double *partial, double *dxi, hipStream_t s);
 
+struct RefineAdam {
+  double lr_rho, lr_omega, beta1, beta2, eps;
+};
+// state: xi[6], m[6], v[6] (device); t = 0 initialises the moments
+hipError_t launch_refine_step(const double *dxi, int F, int t, const RefineAdam &a, double *state, double *xi_frames,
+                              hipStream_t s);
+
 }  // namespace usv

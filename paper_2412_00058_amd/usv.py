@@ -7,12 +7,13 @@ is no CPU path: without the built library every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from typing import Optional, Sequence
 
 import numpy as np
 import torch
 
-from ._lib import Box, GridDesc, ProbeDesc, SegParams, UsvError, check, lib
+from ._lib import Box, GridDesc, ProbeDesc, RefineParams, SegParams, UsvError, check, lib
 
 SEG_ALG2, SEG_ALG1, SEG_FIXED = 0, 1, 2
 EMPTY, MEASURED, FILLED = 0, 1, 2
@@ -352,6 +353,24 @@ class SplatContext:
         dxi = torch.empty((F, 6), dtype=torch.float64, device=I.device) if dxi is None else dxi
         check(lib().usv_splat_backward(self.h, _vp(I), _vp(Tstar), _vp(xi), F, _vp(grads), _vp(dI), _vp(dxi)))
         return dI, dxi
+
+    def refine_motion(self, I, Tstar, xi0=None, iters=150, lr_rho=0.05, lr_omega=math.radians(0.05), beta1=0.9,
+                      beta2=0.999, eps=1e-8, vols=None, grads=None):
+        """Adam on one rigid motion xi (rho mm, omega rad) applied to the odd frames
+        (T_n = Exp(xi) T*_n) that minimises the overlap loss; runs asynchronously on the
+        stream.  Returns (xi [6] fp64, loss [iters + 1] fp64)."""
+        F = I.shape[0]
+        dev = I.device
+        xi = torch.zeros(6, dtype=torch.float64, device=dev)
+        if xi0 is not None:
+            xi.copy_(torch.as_tensor(xi0, dtype=torch.float64))
+        loss = torch.empty(int(iters) + 1, dtype=torch.float64, device=dev)
+        vols = torch.empty((4, self.nvox), dtype=torch.float32, device=dev) if vols is None else vols
+        grads = torch.empty((4, self.nvox), dtype=torch.float32, device=dev) if grads is None else grads
+        prm = RefineParams(int(iters), float(lr_rho), float(lr_omega), float(beta1), float(beta2), float(eps))
+        check(lib().usv_refine_motion(self.h, _vp(I), _vp(Tstar), F, C.byref(prm), _vp(xi), _vp(loss), _vp(vols),
+                                      _vp(grads)))
+        return xi, loss
 
     def close(self):
         if getattr(self, "h", None):

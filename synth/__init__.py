@@ -322,35 +322,40 @@ def cfg5(n_frames: int = 512, W: int = 320, H: int = 240, px: float = 0.4,
                 grid=Grid(tuple(dims), (0.0, 0.0, 0.0), voxel))
 
 
-def motion_case(n_frames: int = 256, W: int = 320, H: int = 240, px: float = 0.4, spacing: float = 0.2,
-                voxel: float = 0.5, n_blobs: int = 24, rho_mm: float = 1.0, omega_deg: float = 1.0):
-    """Pose-refinement workload: frames rendered from world-space Gaussian blobs (as in
-    config 5) at true poses z_n = 0.25 + spacing n mm (closely spaced, so that even and
-    odd frames share voxels); the odd frames' poses are perturbed by xi (rho uniform in
-    +-rho_mm, omega in +-omega_deg), the even frames' are exact."""
+def two_pass_case(n_frames: int = 256, W: int = 320, H: int = 240, px: float = 0.4, spacing: float = 0.2,
+                  voxel: float = 0.5, n_blobs: int = 24, motion_mm=(0.8, -0.6, 0.5), motion_deg=(0.6, -0.5, 0.8)):
+    """Two interleaved passes over world-space Gaussian blobs (as in config 5) with a patient
+    motion between them: frame n is rendered at z_n = 0.25 + spacing n mm; even frames are
+    pass 1, odd frames pass 2.  The patient (world) moved by the rigid transform
+    delta = [R | t] (R = Rz Ry Rx of motion_deg about the grid origin, t = motion_mm) before
+    pass 2, which the tracker did not see: odd frames report Tstar = delta^-1 Ttrue, even
+    frames Tstar = Ttrue.  Undoing the motion means posing the odd frames at delta Tstar."""
     nz = int(math.ceil((0.25 + spacing * n_frames) / voxel)) + 4
     dims = (int(math.ceil(W * px / voxel)), int(math.ceil(H * px / voxel)), nz)
     g = rng(6, 4, 0)
     ext = np.array([W * px, H * px, spacing * n_frames])
     centres = g.uniform(0.1, 0.9, size=(n_blobs, 3)) * ext
     amps = g.uniform(80.0, 200.0, size=n_blobs)
-    T = np.empty((n_frames, 4, 4))
+    Ttrue = np.empty((n_frames, 4, 4))
     I = np.empty((n_frames, H, W), dtype=np.float32)
     for n in range(n_frames):
         A = np.eye(4)
         A[2, 3] = 0.25 + spacing * n
-        T[n] = A
+        Ttrue[n] = A
         X, Y, Z = pixel_world(A, W, H, px, px)
         val = np.zeros((H, W))
         for b in range(n_blobs):
             d2 = (X - centres[b, 0]) ** 2 + (Y - centres[b, 1]) ** 2 + (Z - centres[b, 2]) ** 2
             val += amps[b] * np.exp(-d2 / (2.0 * 16.0))
         I[n] = (np.minimum(val, 255.0) / 255.0).astype(np.float32)
-    gp = rng(6, 3, 0)
-    xi = np.concatenate([gp.uniform(-rho_mm, rho_mm, size=(n_frames, 3)),
-                         gp.uniform(-omega_deg, omega_deg, size=(n_frames, 3)) * (math.pi / 180.0)], axis=1)
-    xi[0::2] = 0.0
-    return dict(I=I, Ttrue=T, xi=xi, probe=Probe(W, H, (px, px)), grid=Grid(dims, (0.0, 0.0, 0.0), voxel))
+    ax, ay, az = (math.radians(d) for d in motion_deg)
+    delta = np.eye(4)
+    delta[:3, :3] = rot_z(az) @ rot_y(ay) @ rot_x(ax)
+    delta[:3, 3] = motion_mm
+    Tstar = Ttrue.copy()
+    Tstar[1::2] = np.linalg.inv(delta) @ Ttrue[1::2]
+    return dict(I=I, Ttrue=Ttrue, Tstar=Tstar, delta=delta, probe=Probe(W, H, (px, px)),
+                grid=Grid(dims, (0.0, 0.0, 0.0), voxel))
 
 
 def small_splat(n_frames: int = 16, W: int = 40, H: int = 30, dims=(32, 24, 16), seed: int = 55):
