@@ -211,6 +211,45 @@ def bench_refine(torch, usv, iters=150):
     return dt * 1e3 / iters, float(np.linalg.norm(E[:3, 3])), ang, float(Lh[-1] / Lh[0])
 
 
+def bench_cut(torch, usv, d, frames, vol, pid, reps=3):
+    """Image-space tissue segmentation on the whole-spine sweep: (ms of the Alg. 2 bands
+    over the 3600-frame device stack, its read rate in GB/s, ms of the whole Spine-volume
+    pass = Alg. 2 bands + band copy to the host + cut ingest in calls of 64 + finalize,
+    mean kept rows per frame)."""
+    F, H, W = frames.shape
+    prm = usv.cut_params(y_lo=100, k=6, tau_I=128, tau_G=40, r=5, fallback_row=370, half_rows=50)
+    scratch = torch.empty(F * (W + 1), dtype=torch.int16, device="cuda")
+    rows = torch.empty((F, 2), dtype=torch.int32, device="cuda")
+    usv.cut_rows_alg2(frames, prm, scratch, rows)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        usv.cut_rows_alg2(frames, prm, scratch, rows)
+    torch.cuda.synchronize()
+    ms_alg2 = (time.perf_counter() - t0) * 1e3 / reps
+    gbps = F * H * W / (ms_alg2 * 1e-3) / 1e9
+    V = torch.empty(tuple(reversed(d["grid"].dims)), dtype=torch.uint8, device="cuda")
+    S = torch.empty_like(V)
+
+    def spine():
+        vol.reset()
+        usv.cut_rows_alg2(frames, prm, scratch, rows)
+        R = rows.cpu().numpy()
+        for k in range(0, F, 64):
+            vol.ingest_cut(pid, frames[k:k + 64], d["poses"][k:k + 64], R[k:k + 64])
+        vol.finalize(out=(V, S))
+        return R
+
+    spine()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        R = spine()
+    torch.cuda.synchronize()
+    ms_spine = (time.perf_counter() - t0) * 1e3 / reps
+    return ms_alg2, gbps, ms_spine, float(np.mean(R[:, 1] - R[:, 0] + 1))
+
+
 def bench_graph(torch, usv, d, n=512, n_lat=200):
     """Real-time path: one frame per captured-graph launch from host memory (pinned
     staging copy, H2D, ingest).  Returns (frames/s back to back, p50 and p99 latency in
@@ -492,6 +531,15 @@ def main():
             extras["fwd_bwd_ms_per_step"] = round(ms, 3)
         except Exception as e:  # report, do not hide
             extras["fwd_bwd_error"] = repr(e)
+        try:
+            ms_a2, gbps, ms_sp, kept_rows = bench_cut(torch, usv, d, frames, vol, pid)
+            extras["cut_alg2_ms"] = round(ms_a2, 3)
+            extras["cut_alg2_read_GBps"] = round(gbps, 1)
+            extras["spine_volume_ms"] = round(ms_sp, 3)
+            extras["spine_volume_frames_per_s"] = round(F / (ms_sp * 1e-3), 1)
+            extras["spine_kept_rows_per_frame"] = round(kept_rows, 1)
+        except Exception as e:
+            extras["cut_error"] = repr(e)
         try:
             ms, rt, ra, drop = bench_refine(torch, usv)
             extras["refine_ms_per_iter"] = round(ms, 4)

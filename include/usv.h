@@ -181,6 +181,53 @@ usv_status usv_segment_project(usv_volume *vol, const usv_seg_params *params, co
                                const uint8_t *state_dev, int16_t *depth_dev, float *mean_dev, float *max_dev);
 
 /* ---------------------------------------------------------------------------------
+ * Image-space tissue segmentation (Sec. II.D, Tables I and II): before compounding,
+ * each frame is cut to a band of rows around its depth of cut (the cut image Img_C),
+ * and the cut images are compounded into a separate "Spine" volume (Table I Step 6,
+ * Table II Step 5).  A band is two int32 per frame, first and last kept row
+ * (inclusive, 0 = top of the image); a band with first > last keeps nothing.
+ * --------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t half_rows;     /* band = [d - half_rows, d + half_rows] clipped to [0, H) */
+  /* Alg. 1 (Table I Step 4) */
+  int32_t axis;          /* world axis along the spine: 0, 1 or 2 */
+  double K;              /* mm of cut per mm along the back */
+  double D_mm;           /* depth of cut at the middle of the back */
+  double L_mm;           /* length of the back */
+  double z1_mm;          /* along-spine position of the first frame's upper-left pixel */
+  /* Alg. 2 (Table II Steps 2-3) */
+  int32_t y_lo, k, tau_I, tau_G;   /* contour scan, as in usv_seg_params */
+  int32_t r;             /* median filter across frames: window [n - r, n + r], 0..64 */
+  int32_t fallback_row;  /* depth when no frame in the window has a contour, in [0, H) */
+} usv_cut_params;
+
+/* Alg. 1 (host, FP64): for frame n, P = (A_n C)[axis][3] (the upper-left pixel along the
+ * spine, products summed in index order), sigma = |P - z1|,
+ * Cut = K |sigma - L/2| + D (mm, Table I Step 4; sign as read for the middle of the
+ * back), d = clamp(floor(Cut / sy), 0, H - 1) (the image row holding that depth).  A
+ * pose that gives no finite Cut keeps nothing.  rows_host: [n][2], written. */
+usv_status usv_cut_rows_alg1(const usv_probe_desc *probe, const double *poses_host, int32_t n,
+                             const usv_cut_params *params, int32_t *rows_host);
+
+/* Alg. 2 (device, on `stream`): per frame f and column u, the contour row of the volume
+ * path's rule (usv_seg_params, ALG2) along the image rows y in [y_lo, H-1-k]; per frame
+ * the lower median of its valid contour rows (-1 if none); then d_f = lower median of the
+ * valid per-frame values over frames [f - r, f + r] (clipped), or fallback_row; band
+ * [d_f - half_rows, d_f + half_rows] clipped to [0, H).  frames_dev: uint8 with the given
+ * pitches.  scratch_dev: F * (W + 1) int16 of caller-owned device memory (contour rows,
+ * then per-frame medians).  rows_dev: [F][2] int32 device output. */
+usv_status usv_cut_rows_alg2(const uint8_t *frames_dev, int64_t row_pitch, int64_t frame_pitch, int32_t F,
+                             int32_t W, int32_t H, const usv_cut_params *params, int16_t *scratch_dev,
+                             int32_t *rows_dev, void *stream);
+
+/* usv_ingest_frames restricted to each frame's band: frame i adds only its pixels of
+ * rows [rows_host[2i], rows_host[2i+1]] (clipped to the image; mask still applies).
+ * dirty_out covers the bands only. */
+usv_status usv_ingest_frames_cut(usv_volume *vol, int32_t probe_id, const uint8_t *frames_dev, int64_t row_pitch,
+                                 int64_t frame_pitch, const double *poses_host, const int32_t *rows_host, int32_t n,
+                                 usv_box *dirty_out);
+
+/* ---------------------------------------------------------------------------------
  * Batched multi-sweep ingest: n_sweeps independent (volume, probe, frames, poses)
  * jobs compounded by one persistent launch on the first volume's stream.  All
  * volumes must live on the same device.  Per sweep the result equals

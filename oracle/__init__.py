@@ -30,12 +30,18 @@ def lib():
         L.orc_fold.argtypes = [P, P, C.c_double, C.c_double, P, C.c_double, P]
         L.orc_fold.restype = None
         L.orc_ingest_nearest.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int,
-                                         C.c_int64, C.c_int64, P, P, C.c_int, P, C.c_int32, P]
+                                         C.c_int64, C.c_int64, P, P, C.c_int, P, C.c_int32, P, P]
         L.orc_ingest_nearest.restype = C.c_int64
         L.orc_finalize.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P]
         L.orc_finalize.restype = C.c_int64
         L.orc_segment.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_double, P, P, P, P, P, P]
         L.orc_segment.restype = None
+        L.orc_cut_rows_alg1.argtypes = [P, P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, C.c_int, P]
+        L.orc_cut_rows_alg1.restype = None
+        L.orc_cut_rows_alg2.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                        C.c_int, C.c_int, P]
+        L.orc_cut_rows_alg2.restype = None
         L.orc_se3_exp.argtypes = [P, P]
         L.orc_se3_left_jacobian.argtypes = [P, P]
         L.orc_splat_forward.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_double, P, P, P, C.c_int, C.c_int,
@@ -91,9 +97,10 @@ class Accum:
         self.stamp = None
         self.stamp_id = 0
 
-    def ingest(self, frames, poses, probe, calib=None, count_distinct=False):
-        """Add frames (uint8 [F][H][W]) taken at poses (FP64 [F][4][4]).  Returns
-        (kept pixels, distinct voxels touched by this call or -1)."""
+    def ingest(self, frames, poses, probe, calib=None, count_distinct=False, rows=None):
+        """Add frames (uint8 [F][H][W]) taken at poses (FP64 [F][4][4]); with rows (int32
+        [F][2], first and last row) only each frame's band.  Returns (kept pixels,
+        distinct voxels touched by this call or -1)."""
         calib = np.eye(4) if calib is None else calib
         frames = _c(frames, np.uint8)
         F, H, W = frames.shape
@@ -110,12 +117,34 @@ class Accum:
         nx, ny, nz = self.grid.dims
         kept = lib().orc_ingest_nearest(nx, ny, nz, _p(self.sum), _p(self.cnt), C.byref(self.overflow),
                                         _p(frames), W, H, W, H * W, _p(M), _p(mask), F,
-                                        stamp_p, self.stamp_id, C.byref(nd))
+                                        stamp_p, self.stamp_id, C.byref(nd),
+                                        None if rows is None else _p(_c(rows, np.int32).reshape(F, 2)))
         return int(kept), (int(nd.value) if count_distinct else -1)
 
     @property
     def overflowed(self) -> bool:
         return bool(self.overflow.value)
+
+
+def cut_rows_alg1(poses, probe, calib=None, axis=2, K=0.0, D_mm=0.0, L_mm=0.0, z1_mm=0.0, half_rows=0):
+    """Table I Steps 2-4 in image space: int32 [F][2] row bands (first, last)."""
+    calib = np.eye(4) if calib is None else calib
+    poses = _c(poses, np.float64).reshape(-1, 16)
+    n = poses.shape[0]
+    rows = np.empty((n, 2), dtype=np.int32)
+    lib().orc_cut_rows_alg1(_p(poses), _p(_c(calib, np.float64)), n, float(probe.pixel_mm[1]), int(probe.height),
+                            int(axis), float(K), float(D_mm), float(L_mm), float(z1_mm), int(half_rows), _p(rows))
+    return rows
+
+
+def cut_rows_alg2(frames, y_lo=0, k=6, tau_I=128, tau_G=40, r=2, fallback_row=0, half_rows=0):
+    """Table II Steps 2-4 in image space: int32 [F][2] row bands (first, last)."""
+    frames = _c(frames, np.uint8)
+    F, H, W = frames.shape
+    rows = np.empty((F, 2), dtype=np.int32)
+    lib().orc_cut_rows_alg2(_p(frames), F, W, H, int(y_lo), int(k), int(tau_I), int(tau_G), int(r),
+                            int(fallback_row), int(half_rows), _p(rows))
+    return rows
 
 
 def finalize(grid, sum_, cnt, fill_min=1):

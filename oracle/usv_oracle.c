@@ -15,6 +15,8 @@
  *   - cut depth from the probe pose: Table I Step 4;
  *   - cut depth from bright / high-gradient contours and a median filter: Table II
  *     Steps 2-3 and the discussion of bone cortex over an acoustic shadow in Sec. II.D;
+ *   - image-space cut (Img_C) of both algorithms before compounding: Table I Steps 4-6,
+ *     Table II Steps 2-5;
  *   - fixed-depth projection (VPI) baseline: Sec. I and Sec. III.B.
  * The differentiable trilinear splat, its loss and its gradient are not in the paper;
  * they follow the definitions written next to each routine.
@@ -70,17 +72,21 @@ void orc_fold(const double *A, const double *C, double sx, double sy, const doub
  *   sum[idx] += I(u, v) (mod 2^32), cnt[idx] += 1 (mod 2^16; a wrap sets *overflow)
  * Returns the number of kept pixels.  If `stamp_buf` is given, it also counts the
  * distinct voxels touched by this call (stamp_buf[idx] != stamp marks a first touch).
+ * If `rows` is given (two int32 per frame, first and last row), frame f contributes
+ * only its rows rows[2f] .. rows[2f+1]: the cut image Img_C of Table I Step 5 /
+ * Table II Step 4, compounded by Table I Step 6 / Table II Step 5.
  * ---------------------------------------------------------------------------------- */
 int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt, int *overflow,
                            const uint8_t *frames, int W, int H, int64_t row_pitch, int64_t frame_pitch,
                            const float *M, const uint8_t *mask, int n_frames,
-                           int32_t *stamp_buf, int32_t stamp, int64_t *n_distinct) {
+                           int32_t *stamp_buf, int32_t stamp, int64_t *n_distinct, const int32_t *rows) {
   int64_t kept = 0;
   const float nf[3] = {(float)nx, (float)ny, (float)nz};
   for (int f = 0; f < n_frames; ++f) {
     const float *m = M + 9 * f;
     const uint8_t *img = frames + (int64_t)f * frame_pitch;
     for (int v = 0; v < H; ++v) {
+      if (rows && (v < rows[2 * f] || v > rows[2 * f + 1])) continue;
       float fv = (float)v;
       float c[3];
       for (int r = 0; r < 3; ++r) {
@@ -293,6 +299,93 @@ void orc_segment(int nx, int ny, int nz, const double *origin, double s, const u
       }
     }
   free(d);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Image-space depth of cut (Sec. II.D), one band of rows per frame: rows[2n] = first
+ * kept row, rows[2n+1] = last (inclusive), band = [d - h, d + h] clipped to [0, H-1].
+ * Alg. 1 (Table I Steps 2-4): P_n = (A_n C)[axis][3], the upper-left pixel of frame n
+ *   along the spine (products in index order, FP64); sigma = |P_n - z1| (z1: the same
+ *   for the first frame); Cut = K |sigma - L/2| + D mm; d = floor(Cut / sy) clamped to
+ *   [0, H-1]; a non-finite Cut keeps nothing (rows = 0, -1).
+ * ---------------------------------------------------------------------------------- */
+void orc_cut_rows_alg1(const double *poses, const double *C, int n, double sy, int H, int axis, double K,
+                       double D_mm, double L_mm, double z1_mm, int h, int32_t *rows) {
+  for (int f = 0; f < n; ++f) {
+    const double *A = poses + 16 * f;
+    double P = A[4 * axis + 0] * C[3];
+    P = P + A[4 * axis + 1] * C[7];
+    P = P + A[4 * axis + 2] * C[11];
+    P = P + A[4 * axis + 3] * C[15];
+    double sigma = fabs(P - z1_mm);
+    double cut = K * fabs(sigma - L_mm / 2.0) + D_mm;
+    double yy = floor(cut / sy);
+    if (!isfinite(yy)) {
+      rows[2 * f] = 0;
+      rows[2 * f + 1] = -1;
+      continue;
+    }
+    int d = yy < 0.0 ? 0 : (yy > (double)(H - 1) ? H - 1 : (int)yy);
+    rows[2 * f] = d - h < 0 ? 0 : d - h;
+    rows[2 * f + 1] = d + h > H - 1 ? H - 1 : d + h;
+  }
+}
+
+/* Alg. 2 (Table II Steps 2-4) on frames [F][H][W] (tightly packed):
+ *   Step 2, per frame f and column u, over rows y in [y_lo, H-1-k]:
+ *     s(y) = k I(y) - sum_{j=1..k} I(y+j); candidate iff I(y) >= tau_I and
+ *     s(y) >= k tau_G; contour row = argmax s over candidates, ties -> largest y;
+ *     none -> -1 (the rule of the volume path, along the image's depth axis);
+ *   Step 3, the median filter over all contour information: c_f = lower median
+ *     (element floor((m-1)/2) of the m valid rows, ascending) of frame f's contour
+ *     rows, -1 if none; d_f = lower median of the valid c over frames [f-r, f+r]
+ *     clipped to the sweep, fallback_row if none;
+ *   Step 4, band [d_f - h, d_f + h] clipped to [0, H-1]. */
+void orc_cut_rows_alg2(const uint8_t *frames, int F, int W, int H, int y_lo, int k, int tau_I, int tau_G, int r,
+                       int fallback_row, int h, int32_t *rows) {
+  int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)(F > 0 ? F : 1));
+  int32_t *col = (int32_t *)malloc(sizeof(int32_t) * (size_t)W);
+  for (int f = 0; f < F; ++f) {
+    const uint8_t *img = frames + (int64_t)f * W * H;
+    int m = 0;
+    for (int u = 0; u < W; ++u) {
+      int32_t best = -1;
+      int64_t best_s = 0;
+      for (int y = y_lo; y <= H - 1 - k; ++y) {
+        int64_t here = img[(int64_t)y * W + u];
+        int64_t below = 0;
+        for (int j = 1; j <= k; ++j) below += img[(int64_t)(y + j) * W + u];
+        int64_t sc = (int64_t)k * here - below;
+        if (here >= tau_I && sc >= (int64_t)k * tau_G && (best < 0 || sc >= best_s)) {
+          best = y;
+          best_s = sc;
+        }
+      }
+      if (best >= 0) col[m++] = best;
+    }
+    if (m == 0) {
+      c[f] = -1;
+    } else {
+      qsort(col, (size_t)m, sizeof(int32_t), cmp_i32);
+      c[f] = col[(m - 1) / 2];
+    }
+  }
+  int32_t *win = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * r + 1));
+  for (int f = 0; f < F; ++f) {
+    int m = 0;
+    for (int g = f - r; g <= f + r; ++g)
+      if (g >= 0 && g < F && c[g] >= 0) win[m++] = c[g];
+    int d = fallback_row;
+    if (m > 0) {
+      qsort(win, (size_t)m, sizeof(int32_t), cmp_i32);
+      d = win[(m - 1) / 2];
+    }
+    rows[2 * f] = d - h < 0 ? 0 : d - h;
+    rows[2 * f + 1] = d + h > H - 1 ? H - 1 : d + h;
+  }
+  free(win);
+  free(col);
+  free(c);
 }
 
 /* ------------------------------------------------------------------------------------

@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "USV_OK", -1: "USV_E_ARG", -2: "USV_E_OOM", -3: "USV_E_DEVICE
 EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
-    "usv_ingest_frames", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
+    "usv_ingest_frames", "usv_ingest_frames_cut", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
     "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
     "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
@@ -49,6 +49,12 @@ class SegParams(C.Structure):
                 ("tau_G", C.c_int32), ("r", C.c_int32), ("fallback_y", C.c_int32), ("n_half", C.c_int32),
                 ("half", C.c_int32 * 4), ("K", C.c_double), ("D_mm", C.c_double), ("L_mm", C.c_double),
                 ("z1_mm", C.c_double), ("yref_mm", C.c_double)]
+
+
+class CutParams(C.Structure):
+    _fields_ = [("half_rows", C.c_int32), ("axis", C.c_int32), ("K", C.c_double), ("D_mm", C.c_double),
+                ("L_mm", C.c_double), ("z1_mm", C.c_double), ("y_lo", C.c_int32), ("k", C.c_int32),
+                ("tau_I", C.c_int32), ("tau_G", C.c_int32), ("r", C.c_int32), ("fallback_row", C.c_int32)]
 
 
 class RefineParams(C.Structure):
@@ -87,6 +93,9 @@ def lib():
         "usv_destroy_volume": (I32, [P]),
         "usv_last_error": (C.c_char_p, [P]),
         "usv_ingest_frames": (I32, [P, I32, P, I64, I64, P, I32, C.POINTER(Box)]),
+        "usv_ingest_frames_cut": (I32, [P, I32, P, I64, I64, P, P, I32, C.POINTER(Box)]),
+        "usv_cut_rows_alg1": (I32, [C.POINTER(ProbeDesc), P, I32, C.POINTER(CutParams), P]),
+        "usv_cut_rows_alg2": (I32, [P, I64, I64, I32, I32, I32, C.POINTER(CutParams), P, P, P]),
         "usv_finalize": (I32, [P, C.POINTER(Box), P, P]),
         "usv_segment_project": (I32, [P, C.POINTER(SegParams), P, P, P, P, P]),
         "usv_ingest_batched": (I32, [P, P, P, P, P, P, P, I32, P]),

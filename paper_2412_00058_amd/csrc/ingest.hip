@@ -102,11 +102,11 @@ __device__ __forceinline__ void load_rows(const SweepDesc &d, const uint8_t *__r
 
 // Pixel phase.  kFast: full tile, window inside the grid, no mask, LDS window, rows
 // already loaded -- no per-pixel test at all.
-template <bool kAligned, bool kFast>
+template <bool kAligned, bool kFast, bool kRows = false>
 __device__ __forceinline__ uint32_t pixel_phase(const SweepDesc &d, const uint8_t *__restrict__ img, const float m[9],
                                                 const Win &w, int cls, int u0, int u1, int v0, int v1,
                                                 const LaneGeo &lg, const uint32_t pre[kMaxKr], uint32_t *win,
-                                                const float4 *ctab) {
+                                                const float4 *ctab, int vlo = 0) {
   const Tiling &t = d.t;
   const int u = u0 + lg.uoff;
   uint32_t direct_kept = 0u;
@@ -147,7 +147,7 @@ __device__ __forceinline__ uint32_t pixel_phase(const SweepDesc &d, const uint8_
   for (int k = 0; k < kMaxKr; ++k) {
     px[k] = 0u;
     const int v = vb + k;
-    if (k < t.kr && v <= v1) {
+    if (k < t.kr && v <= v1 && (!kRows || v >= vlo)) {
       const uint8_t *row = img + (int64_t)v * d.row_pitch;
       if (wide) {
         px[k] = *reinterpret_cast<const uint32_t *>(row + u);
@@ -160,6 +160,7 @@ __device__ __forceinline__ uint32_t pixel_phase(const SweepDesc &d, const uint8_
   for (int k = 0; k < kMaxKr; ++k) {
     const int v = vb + k;
     if (k >= t.kr || v > v1) break;
+    if (kRows && v < vlo) continue;
     uint32_t ok = colmask;
     if (cls == 1) {
       if (d.spans) {
@@ -268,24 +269,32 @@ struct Smem {
 // Compound one tile (one block).  The lane's pixel rows of a full tile are loaded first,
 // so that they arrive while the window is set up.  Waves retire right after issuing
 // their flush atomics (no atomic returns a value), so no wave ever waits for them.
-template <bool kAligned>
+// kRows: only image rows [vlo, vhi] of this frame are compounded (the cut image of the
+// tissue segmentation); tiles outside the band leave at once, tiles cut by it take the
+// per-pixel path.
+template <bool kAligned, bool kRows = false>
 __device__ __forceinline__ void tile_once(const SweepDesc &d, const uint8_t *__restrict__ img, const float m[9],
-                                          int tr, int tc, Smem &sm) {
+                                          int tr, int tc, Smem &sm, int vlo = 0, int vhi = 0) {
   const Tiling &t = d.t;
   const int tid = threadIdx.x;
   const int cls = d.tile_class ? d.tile_class[tr * t.tiles_x + tc] : 0;
   if (cls == 2) return;
   const int u0 = tc * t.tw, v0 = tr * t.th;
-  const int u1 = min(u0 + t.tw, d.W) - 1, v1 = min(v0 + t.th, d.H) - 1;
+  int v1 = min(v0 + t.th, d.H) - 1;
+  const int u1 = min(u0 + t.tw, d.W) - 1;
+  if (kRows) {
+    if (v1 < vlo || v0 > vhi) return;
+    v1 = min(v1, vhi);
+  }
   const LaneGeo lg = lane_geo(t);
-  const bool full = kAligned && u0 + t.tw <= d.W && v0 + t.th <= d.H;
+  const bool full = kAligned && u0 + t.tw <= d.W && v0 + t.th <= d.H && (!kRows || (v0 >= vlo && v0 + t.th - 1 <= vhi));
   uint32_t px[kMaxKr] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   if (full) load_rows(d, img, tr, tc, lg, px);
 
   Win w;
   int hi0, hi1, hi2;
   bool inside = true;
-  const float fu0 = (float)u0, fu1 = (float)u1, fv0 = (float)v0, fv1 = (float)v1;
+  const float fu0 = (float)u0, fu1 = (float)u1, fv0 = (float)(kRows ? max(v0, vlo) : v0), fv1 = (float)v1;
   if (!axis_range(m[0], m[1], m[2], fu0, fu1, fv0, fv1, d.nx, w.lo0, hi0, inside)) return;
   if (!axis_range(m[3], m[4], m[5], fu0, fu1, fv0, fv1, d.ny, w.lo1, hi1, inside)) return;
   if (!axis_range(m[6], m[7], m[8], fu0, fu1, fv0, fv1, d.nz, w.lo2, hi2, inside)) return;
@@ -331,7 +340,7 @@ __device__ __forceinline__ void tile_once(const SweepDesc &d, const uint8_t *__r
   if (full && inside && !w.direct && cls == 0)
     pixel_phase<kAligned, true>(d, img, m, w, cls, u0, u1, v0, v1, lg, px, sm.win, sm.ctab);
   else
-    kept = pixel_phase<kAligned, false>(d, img, m, w, cls, u0, u1, v0, v1, lg, px, sm.win, sm.ctab);
+    kept = pixel_phase<kAligned, false, kRows>(d, img, m, w, cls, u0, u1, v0, v1, lg, px, sm.win, sm.ctab, vlo);
   if (!w.direct) {
     __syncthreads();
     if (pairs) kept += flush_window<true, false>(d, w, sm.win, sm.rowtab);
@@ -343,10 +352,10 @@ __device__ __forceinline__ void tile_once(const SweepDesc &d, const uint8_t *__r
 // Launch over the frames of one call: block = (frame, tile row, tile column) with the
 // column fastest, so consecutive blocks (placed round-robin on the 8 XCDs) cover the
 // columns of one tile row.  kDevMaps: maps and frame indices in device memory.
-template <bool kAligned, bool kDevMaps>
+template <bool kAligned, bool kDevMaps, bool kRows = false>
 __device__ __forceinline__ void run_block(const SweepDesc &d, const float *__restrict__ Mdev,
                                           const int32_t *__restrict__ fdev, const float (*Marg)[9],
-                                          const int32_t *farg, Smem &sm) {
+                                          const int32_t *farg, Smem &sm, const uint32_t *rows = nullptr) {
   const Tiling &t = d.t;
   const uint32_t it = blockIdx.x;
   const uint32_t per_frame = (uint32_t)(t.tiles_x * t.tiles_y);
@@ -365,7 +374,13 @@ __device__ __forceinline__ void run_block(const SweepDesc &d, const float *__res
     for (int i = 0; i < 9; ++i) m[i] = Marg[f][i];
     fi = farg[f];
   }
-  tile_once<kAligned>(d, d.frames + (int64_t)fi * d.frame_pitch, m, tr, tc, sm);
+  if (kRows) {
+    const uint32_t b = rows[f];
+    tile_once<kAligned, true>(d, d.frames + (int64_t)fi * d.frame_pitch, m, tr, tc, sm, (int)(b & 0xFFFFu),
+                              (int)(b >> 16));
+  } else {
+    tile_once<kAligned>(d, d.frames + (int64_t)fi * d.frame_pitch, m, tr, tc, sm);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void ingest_kernel(IngestLaunch a) {
@@ -378,6 +393,19 @@ __global__ __launch_bounds__(kBlock) void ingest_kernel_bytes(IngestLaunch a) {
   __shared__ __align__(16) Smem sm;
   const SweepDesc d = a.d;
   run_block<false, false>(d, nullptr, nullptr, a.M, a.fidx, sm);
+}
+
+// With a band of image rows per frame (rows in the argument segment too).
+__global__ __launch_bounds__(kBlock) void ingest_kernel_rows(IngestLaunchRows a) {
+  __shared__ __align__(16) Smem sm;
+  const SweepDesc d = a.a.d;
+  run_block<true, false, true>(d, nullptr, nullptr, a.a.M, a.a.fidx, sm, a.rows);
+}
+
+__global__ __launch_bounds__(kBlock) void ingest_kernel_rows_bytes(IngestLaunchRows a) {
+  __shared__ __align__(16) Smem sm;
+  const SweepDesc d = a.a.d;
+  run_block<false, false, true>(d, nullptr, nullptr, a.a.M, a.a.fidx, sm, a.rows);
 }
 
 // The same with the maps in device memory (used by captured graphs, whose launch
@@ -481,6 +509,17 @@ hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s) {
     hipLaunchKernelGGL(ingest_kernel, dim3(n_items), dim3(kBlock), 0, s, a);
   else
     hipLaunchKernelGGL(ingest_kernel_bytes, dim3(n_items), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest_rows(const IngestLaunchRows &a, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const bool aligned = (a.a.d.row_pitch % 4 == 0) && (a.a.d.frame_pitch % 4 == 0) &&
+                       ((((uintptr_t)a.a.d.frames) & 3u) == 0);
+  if (aligned)
+    hipLaunchKernelGGL(ingest_kernel_rows, dim3(n_items), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(ingest_kernel_rows_bytes, dim3(n_items), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -184,8 +184,11 @@ MapKind classify_map(const float M[9]) {
 
 // Exact voxel box of one frame: the same FP32 operations as the kernel, evaluated at the
 // corner that extremises each coordinate (monotone in u and in v).
-bool frame_box(const float M[9], int W, int H, const int n[3], int lo[3], int hi[3]) {
-  const float u0 = 0.0f, u1 = (float)(W - 1), v0 = 0.0f, v1 = (float)(H - 1);
+// Voxel box of image rows [vlo, vhi] (all columns): the FP32 coordinate of each axis is
+// monotone in u and in v, so its extremes sit at the corners, evaluated with the kernel's
+// exact operation order.
+bool frame_box_rows(const float M[9], int W, int vlo, int vhi, const int n[3], int lo[3], int hi[3]) {
+  const float u0 = 0.0f, u1 = (float)(W - 1), v0 = (float)vlo, v1 = (float)vhi;
   for (int r = 0; r < 3; ++r) {
     const float m0 = M[3 * r], m1 = M[3 * r + 1], m2 = M[3 * r + 2];
     const float umin = m0 >= 0.0f ? u0 : u1, umax = m0 >= 0.0f ? u1 : u0;
@@ -203,6 +206,10 @@ bool frame_box(const float M[9], int W, int H, const int n[3], int lo[3], int hi
     hi[r] = (qmax < nf ? (int)qmax : n[r] - 1) + 1;
   }
   return true;
+}
+
+bool frame_box(const float M[9], int W, int H, const int n[3], int lo[3], int hi[3]) {
+  return frame_box_rows(M, W, 0, H - 1, n, lo, hi);
 }
 
 void box_union(usv_box &b, const int lo[3], const int hi[3]) {
@@ -361,13 +368,19 @@ double max_pixels_per_voxel(const float M[9], int W, int H) {
 }
 
 // Fold + classify + dirty box for n poses.  Fills maps/fidx of the kept frames.
+// With rows_in ([n][2] inclusive row bands), frames keep only their band: empty bands
+// are skipped, the box covers the band, and the packed bands (lo | hi << 16) of the kept
+// frames go to rows / srows beside fidx / sfidx.
 usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *poses, int32_t n, std::vector<float> &maps,
                           std::vector<int32_t> &fidx, usv_box *box, std::vector<float> *smaps = nullptr,
-                          std::vector<int32_t> *sfidx = nullptr) {
+                          std::vector<int32_t> *sfidx = nullptr, const int32_t *rows_in = nullptr,
+                          std::vector<uint32_t> *rows = nullptr, std::vector<uint32_t> *srows = nullptr) {
   maps.clear();
   fidx.clear();
   if (smaps) smaps->clear();
   if (sfidx) sfidx->clear();
+  if (rows) rows->clear();
+  if (srows) srows->clear();
   usv_box b = empty_box();
   const int dims[3] = {v->nx, v->ny, v->nz};
   for (int32_t i = 0; i < n; ++i) {
@@ -377,15 +390,24 @@ usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *pose
     if (k == MAP_BAD) return fail(v, USV_E_ARG, "pose places the image beyond 2^64 voxels");
     if (k == MAP_SKIP) continue;
     int lo[3], hi[3];
-    if (!frame_box(M, p.W, p.H, dims, lo, hi)) continue;   // no pixel can land in the grid
+    int vlo = 0, vhi = p.H - 1;
+    if (rows_in) {
+      vlo = std::max(rows_in[2 * (size_t)i], 0);
+      vhi = std::min(rows_in[2 * (size_t)i + 1], p.H - 1);
+      if (vlo > vhi) continue;   // nothing of this frame is kept
+    }
+    if (!frame_box_rows(M, p.W, vlo, vhi, dims, lo, hi)) continue;   // no pixel can land in the grid
     box_union(b, lo, hi);
+    const uint32_t band = (uint32_t)vlo | ((uint32_t)vhi << 16);
     if (p.t.cshift != 20 && max_pixels_per_voxel(M, p.W, p.H) > kBigTileMaxPerVoxel) {
       if (!smaps) return fail(v, USV_E_STATE, "frame needs the small-tile tiling");
       smaps->insert(smaps->end(), M, M + 9);
       sfidx->push_back(i);
+      if (srows) srows->push_back(band);
     } else {
       maps.insert(maps.end(), M, M + 9);
       fidx.push_back(i);
+      if (rows) rows->push_back(band);
     }
   }
   if (box) *box = b;
@@ -394,9 +416,10 @@ usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *pose
 
 usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
                          int64_t frame_pitch, const std::vector<float> &maps, const std::vector<int32_t> &fidx,
-                         bool safe = false) {
+                         bool safe = false, const std::vector<uint32_t> *rows = nullptr) {
   const int nk = (int)fidx.size();
-  IngestLaunch a{};
+  IngestLaunchRows r{};
+  IngestLaunch &a = r.a;
   a.d = make_desc(v, p, frames, row_pitch, frame_pitch, safe);
   const int per_frame = a.d.t.tiles_x * a.d.t.tiles_y;
   const int chunk = std::max(1, std::min(p.chunk, kLaunchFrames));
@@ -406,8 +429,11 @@ usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *fram
     for (int i = 0; i < cnt; ++i) {
       a.fidx[i] = fidx[f0 + i];
       for (int j = 0; j < 9; ++j) a.M[i][j] = maps[(size_t)(f0 + i) * 9 + j];
+      if (rows) r.rows[i] = (*rows)[(size_t)(f0 + i)];
     }
-    usv_status st = check_hip(v, launch_ingest(a, cnt * per_frame, v->stream), "ingest launch");
+    const hipError_t e = rows ? launch_ingest_rows(r, cnt * per_frame, v->stream)
+                              : launch_ingest(a, cnt * per_frame, v->stream);
+    usv_status st = check_hip(v, e, "ingest launch");
     if (st != USV_OK) return st;
   }
   return USV_OK;
@@ -624,6 +650,32 @@ usv_status usv_ingest_frames(usv_volume *v, int32_t probe_id, const uint8_t *fra
   return launch_frames(v, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
 }
 
+usv_status usv_ingest_frames_cut(usv_volume *v, int32_t probe_id, const uint8_t *frames, int64_t row_pitch,
+                                 int64_t frame_pitch, const double *poses, const int32_t *rows, int32_t n,
+                                 usv_box *dirty_out) {
+  if (!v) return USV_E_ARG;
+  if (dirty_out) *dirty_out = empty_box();
+  if (probe_id < 0 || probe_id >= (int32_t)v->probes.size()) return fail(v, USV_E_ARG, "unknown probe");
+  if (n < 0 || (n > 0 && (!frames || !poses || !rows))) return fail(v, USV_E_ARG, "null frames / poses / rows");
+  const ProbeState &p = v->probes[(size_t)probe_id];
+  if (row_pitch < p.W || (n > 1 && frame_pitch < (int64_t)(p.H - 1) * row_pitch + p.W) || frame_pitch < 0)
+    return fail(v, USV_E_ARG, "pitch smaller than the image");
+  if (v->sticky == USV_E_DEVICE) return v->sticky;
+  if (n == 0) return USV_OK;
+  std::vector<float> maps, smaps;
+  std::vector<int32_t> fidx, sfidx;
+  std::vector<uint32_t> rk, srk;
+  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, dirty_out, &smaps, &sfidx, rows, &rk, &srk);
+  if (st != USV_OK) {
+    if (dirty_out) *dirty_out = empty_box();
+    return st;
+  }
+  v->count_dirty = true;
+  st = launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx, false, &rk);
+  if (st != USV_OK || sfidx.empty()) return st;
+  return launch_frames(v, p, frames, row_pitch, frame_pitch, smaps, sfidx, true, &srk);
+}
+
 usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, uint8_t *state) {
   if (!v || !vol_u8) return fail(v, USV_E_ARG, "null output");
   if (v->sticky == USV_E_DEVICE) return v->sticky;
@@ -695,6 +747,8 @@ usv_status usv_segment_project(usv_volume *v, const usv_seg_params *pr, const ui
   a.origin_y = v->origin[1];
   a.origin_z = v->origin[2];
   a.s = v->s;
+  a.row_pitch = v->nx;
+  a.plane_pitch = (int64_t)v->nx * v->ny;
   return check_hip(v, launch_segment(a, v->stream), "segment launch");
 }
 

@@ -39,7 +39,6 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
   int bx, z;
   if (!xcd_block((a.nx + 64 * kC - 1) / (64 * kC), a.nz, bx, z)) return;   // uniform per block
   const int x = (bx * 64 + lane) * kC;   // first column of this lane
-  const int64_t nxy = (int64_t)a.nx * a.ny;
   const int ymax = a.ny - 1 - a.k;
   int best[kC], best_s[kC];
 #pragma unroll
@@ -48,11 +47,11 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
     best_s[c] = 0;
   }
   auto row = [&](const uint8_t *col, int y) -> uint32_t {
-    if (kC == 4) return *reinterpret_cast<const uint32_t *>(col + (int64_t)y * a.nx);
-    return col[(int64_t)y * a.nx];
+    if (kC == 4) return *reinterpret_cast<const uint32_t *>(col + (int64_t)y * a.row_pitch);
+    return col[(int64_t)y * a.row_pitch];
   };
   if (x < a.nx && ymax >= a.y_lo) {
-    const uint8_t *col = a.V + (int64_t)z * nxy + x;
+    const uint8_t *col = a.V + (int64_t)z * a.plane_pitch + x;
     const int len = ymax - a.y_lo + 1;
     const int per = (len + kSeg - 1) / kSeg;
     const int yhi = ymax - seg * per;                  // this segment: y in [ylo, yhi]
@@ -231,13 +230,17 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
 
 }  // namespace
 
+hipError_t launch_contour(const SegArgs &a, hipStream_t s) {
+  if (a.nx % 4 == 0 && a.row_pitch % 4 == 0 && a.plane_pitch % 4 == 0 && (((uintptr_t)a.V) & 3u) == 0)
+    hipLaunchKernelGGL(raw_depth_kernel<4>, dim3(xcd_blocks((a.nx + 255) / 256, a.nz)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(raw_depth_kernel<1>, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_segment(const SegArgs &a, hipStream_t s) {
   if (a.mode == 0) {
-    if (a.nx % 4 == 0 && (((uintptr_t)a.V) & 3u) == 0)
-      hipLaunchKernelGGL(raw_depth_kernel<4>, dim3(xcd_blocks((a.nx + 255) / 256, a.nz)), dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL(raw_depth_kernel<1>, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), dim3(256), 0, s, a);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_contour(a, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(depth_slab_kernel, dim3(xcd_blocks((a.nx + SX - 1) / SX, (a.nz + SZ - 1) / SZ)), dim3(256), 0, s,

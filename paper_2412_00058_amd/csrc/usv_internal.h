@@ -58,6 +58,13 @@ struct IngestLaunch {
   float M[kLaunchFrames][9];       // per frame: rows r = (du, dv, const)
 };
 
+// The same with a band of image rows per frame (the cut image of the tissue
+// segmentation): frame i of the launch keeps rows [rows[i] & 0xFFFF, rows[i] >> 16].
+struct IngestLaunchRows {
+  IngestLaunch a;
+  uint32_t rows[kLaunchFrames];
+};
+
 // Batched ingest: a flat list of (sweep, frame, tile) items in one launch.
 struct BatchSweep {
   SweepDesc d;
@@ -77,6 +84,7 @@ struct BatchLaunch {
 // n_items = frames x tiles, one block per item
 hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s);
 hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t s);
+hipError_t launch_ingest_rows(const IngestLaunchRows &a, int n_items, hipStream_t s);
 hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t *fidx, int n_frames, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n_words, hipStream_t s);
 // Sum of all uint16 counts (cnt32 words) compared with the sum of the kept slots; a
@@ -114,8 +122,17 @@ struct SegArgs {
   int32_t half[4];
   double K, D_mm, L_mm, z1_mm, yref_mm;
   double origin_y, origin_z, s;
+  int64_t row_pitch, plane_pitch;   // bytes between y rows / z planes of V (contour scan)
 };
 hipError_t launch_segment(const SegArgs &a, hipStream_t s);
+// Table II Step 2 alone (raw contour depths into a.raw [nz][nx]) over any uint8 stack
+// laid out [z][y][x] with the pitches above: the volume, or a stack of frames [F][H][W].
+hipError_t launch_contour(const SegArgs &a, hipStream_t s);
+// Image-space cut (Table II Step 3 and Step 4 on frames): per frame the lower median of
+// its valid contour rows raw[f][0..W), then per frame the lower median of those over
+// frames [f-r, f+r] (fallback when none) and the band [d - h, d + h] clipped to [0, H).
+hipError_t launch_image_cut(const int16_t *raw, int F, int W, int H, int r, int fallback, int h, int16_t *cn,
+                            int32_t *rows, hipStream_t s);
 
 // ---- differentiable splat ------------------------------------------------------------------
 

@@ -13,7 +13,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import Box, GridDesc, ProbeDesc, RefineParams, SegParams, UsvError, check, lib
+from ._lib import Box, CutParams, GridDesc, ProbeDesc, RefineParams, SegParams, UsvError, check, lib
 
 SEG_ALG2, SEG_ALG1, SEG_FIXED = 0, 1, 2
 EMPTY, MEASURED, FILLED = 0, 1, 2
@@ -64,6 +64,35 @@ def seg_params(mode=SEG_ALG2, y_lo=0, k=6, tau_I=128, tau_G=40, r=2, fallback_y=
         p.half[i] = int(h)
     p.K, p.D_mm, p.L_mm, p.z1_mm, p.yref_mm = K, D_mm, L_mm, z1_mm, yref_mm
     return p
+
+
+def cut_params(half_rows=10, axis=2, K=0.04, D_mm=35.0, L_mm=560.0, z1_mm=0.0, y_lo=0, k=6, tau_I=128, tau_G=40,
+               r=2, fallback_row=0) -> CutParams:
+    """Parameters of the image-space cut (Alg. 1 uses axis..z1_mm, Alg. 2 y_lo..fallback_row)."""
+    return CutParams(int(half_rows), int(axis), float(K), float(D_mm), float(L_mm), float(z1_mm), int(y_lo), int(k),
+                     int(tau_I), int(tau_G), int(r), int(fallback_row))
+
+
+def cut_rows_alg1(width, height, pixel_mm, poses, params: CutParams, calib=None) -> np.ndarray:
+    """Table I Steps 2-4: int32 [F, 2] row bands (first, last) from the poses (host)."""
+    P = _poses(poses)
+    rows = np.empty((P.shape[0], 2), dtype=np.int32)
+    pd, _ = probe_desc(width, height, pixel_mm, calib)
+    check(lib().usv_cut_rows_alg1(C.byref(pd), P.ctypes.data_as(C.c_void_p), P.shape[0], C.byref(params),
+                                  rows.ctypes.data_as(C.c_void_p)))
+    return rows
+
+
+def cut_rows_alg2(frames: torch.Tensor, params: CutParams, scratch=None, rows=None) -> torch.Tensor:
+    """Table II Steps 2-4 on a uint8 device stack [F, H, W]: int32 [F, 2] row bands on the
+    device, computed on the current stream."""
+    assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3 and frames.stride(2) == 1
+    F, H, W = frames.shape
+    scratch = torch.empty(F * (W + 1), dtype=torch.int16, device=frames.device) if scratch is None else scratch
+    rows = torch.empty((F, 2), dtype=torch.int32, device=frames.device) if rows is None else rows
+    check(lib().usv_cut_rows_alg2(_vp(frames), frames.stride(1), frames.stride(0), F, W, H, C.byref(params),
+                                  _vp(scratch), _vp(rows), _stream_ptr()))
+    return rows
 
 
 def _poses(poses) -> np.ndarray:
@@ -143,6 +172,22 @@ class Volume:
         box = Box()
         check(lib().usv_ingest_frames(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                       P.ctypes.data_as(C.c_void_p), n, C.byref(box)), self.h)
+        return box
+
+    def ingest_cut(self, probe_id, frames: torch.Tensor, poses, rows) -> Box:
+        """ingest() restricted to each frame's band of rows (int32 [F, 2] first/last row,
+        host array or tensor): the cut images Img_C of the tissue segmentation."""
+        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3
+        assert frames.stride(2) == 1
+        P = _poses(poses)
+        n = frames.shape[0]
+        R = rows.cpu().numpy() if isinstance(rows, torch.Tensor) else np.asarray(rows)
+        R = np.ascontiguousarray(R, dtype=np.int32).reshape(-1, 2)
+        assert P.shape[0] == n and R.shape[0] == n
+        box = Box()
+        check(lib().usv_ingest_frames_cut(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
+                                          P.ctypes.data_as(C.c_void_p), R.ctypes.data_as(C.c_void_p), n,
+                                          C.byref(box)), self.h)
         return box
 
     def finalize(self, region: Optional[Box] = None, out=None, with_state=True):
