@@ -414,10 +414,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.extras_only:
-        print(json.dumps({"extras_only": True, "fwd_bwd": bench_splat(torch, usv, 3),
-                          "graph": bench_graph(torch, usv, d, n=128, n_lat=32),
-                          "refine": bench_refine(torch, usv, 20),
-                          "batched": bench_batched(torch, usv, 1)}))
+        out = {"extras_only": True, "fwd_bwd": bench_splat(torch, usv, 3),
+               "graph": bench_graph(torch, usv, d, n=128, n_lat=32),
+               "refine": bench_refine(torch, usv, 20),
+               "batched": bench_batched(torch, usv, 1)}
+        g, p = d["grid"], d["probe"]
+        frames = torch.from_numpy(d["frames"]).cuda()
+        vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+        pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+        out["cut"] = bench_cut(torch, usv, d, frames, vol, pid, reps=2)
+        print(json.dumps(out))
         return
 
     g, p = d["grid"], d["probe"]
