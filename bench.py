@@ -250,6 +250,51 @@ def bench_cut(torch, usv, d, frames, vol, pid, reps=3):
     return ms_alg2, gbps, ms_spine, float(np.mean(R[:, 1] - R[:, 0] + 1))
 
 
+def bench_variants(torch, usv, d, frames, reps=2):
+    """The comparison compounding rules on the whole-spine sweep, calls of 64 frames:
+    (ms of voxel-nearest-neighbour ingest + finalize with dmax 0.5 mm, ms of
+    distance-weighted (tent kernel) ingest + finalize)."""
+    g, p = d["grid"], d["probe"]
+    F = frames.shape[0]
+    vn = usv.VNN(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, 0.5)
+    P = [np.ascontiguousarray(d["poses"][k:k + 64]) for k in range(0, F, 64)]
+
+    def vnn_pass():
+        vn.reset()
+        for i, k in enumerate(range(0, F, 64)):
+            vn.ingest(frames[k:k + 64], P[i])
+        return vn.finalize()
+
+    vnn_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        vnn_pass()
+    torch.cuda.synchronize()
+    ms_vnn = (time.perf_counter() - t0) * 1e3 / reps
+    vn.close()
+    del vn
+    ctx = usv.SplatContext(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, 64)
+    Pd = torch.from_numpy(np.ascontiguousarray(d["poses"])).cuda()
+    acc = ctx.dw_clear()
+
+    def dw_pass():
+        ctx.dw_clear(acc)
+        for k in range(0, F, 64):
+            ctx.dw_ingest(acc, frames[k:k + 64], Pd[k:k + 64])
+        return ctx.dw_finalize(acc, 0.05)
+
+    dw_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dw_pass()
+    torch.cuda.synchronize()
+    ms_dw = (time.perf_counter() - t0) * 1e3 / reps
+    ctx.close()
+    return ms_vnn, ms_dw
+
+
 def bench_graph(torch, usv, d, n=512, n_lat=200):
     """Real-time path: one frame per captured-graph launch from host memory (pinned
     staging copy, H2D, ingest).  Returns (frames/s back to back, p50 and p99 latency in
@@ -423,6 +468,7 @@ def main():
         vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
         pid = vol.add_probe(p.width, p.height, p.pixel_mm)
         out["cut"] = bench_cut(torch, usv, d, frames, vol, pid, reps=2)
+        out["variants"] = bench_variants(torch, usv, d, frames, reps=1)
         print(json.dumps(out))
         return
 
@@ -546,6 +592,14 @@ def main():
             extras["spine_kept_rows_per_frame"] = round(kept_rows, 1)
         except Exception as e:
             extras["cut_error"] = repr(e)
+        try:
+            ms_vnn, ms_dw = bench_variants(torch, usv, d, frames)
+            extras["vnn_ms_per_sweep"] = round(ms_vnn, 3)
+            extras["vnn_frames_per_s"] = round(F / (ms_vnn * 1e-3), 1)
+            extras["dw_ms_per_sweep"] = round(ms_dw, 3)
+            extras["dw_frames_per_s"] = round(F / (ms_dw * 1e-3), 1)
+        except Exception as e:
+            extras["variants_error"] = repr(e)
         try:
             ms, rt, ra, drop = bench_refine(torch, usv)
             extras["refine_ms_per_iter"] = round(ms, 4)

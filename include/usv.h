@@ -228,6 +228,37 @@ usv_status usv_ingest_frames_cut(usv_volume *vol, int32_t probe_id, const uint8_
                                  usv_box *dirty_out);
 
 /* ---------------------------------------------------------------------------------
+ * Voxel-nearest-neighbour (VNN) compounding: one of the reconstruction rules of the
+ * review the paper cites when it chooses pixel-nearest-neighbour (Sec. II.C); offered
+ * beside the PNN path for comparison.  Every voxel takes the value of the pixel whose
+ * centre is nearest to the voxel centre, over all frames whose image rectangle the
+ * voxel projects into and whose plane lies within dmax_mm of it; ties go to the earlier
+ * frame (frames are numbered in ingest order since create / reset).  Exact definition,
+ * in the order the library evaluates it (FP32 after an FP64 fold):
+ *   T = A C; map row m (m = a, b, h; scale = sx, sy, 1):
+ *     (T[0][m] s, T[1][m] s, T[2][m] s,
+ *      ((T[0][m] (o0 + s/2 - T[0][3]) + T[1][m] (o1 + s/2 - T[1][3])) + T[2][m] (o2 + s/2 - T[2][3])))
+ *     / scale_m, rounded once to FP32;
+ *   q_m = (fl(N0 i) + fl(N1 j)) + (fl(N2 k) + N3) for voxel (i, j, k);
+ *   reached iff 0 <= q_a < W, 0 <= q_b < H, |q_h| <= dmax and mask(u, v) with
+ *   u = floor q_a, v = floor q_b; d2 = ((q_a - (u+1/2)) sx)^2 + ((q_b - (v+1/2)) sy)^2 + q_h^2.
+ * State: caller-owned keys_dev, 8 bytes per voxel (8-byte aligned), key =
+ * bits(d2) << 32 | frame << 8 | value (~0: not reached).  At most 2^24 frames per
+ * reset.  Calls are ordered on `stream`. */
+typedef struct usv_vnn usv_vnn;
+usv_status usv_vnn_create(const usv_grid_desc *grid, const usv_probe_desc *probe, double dmax_mm, void *keys_dev,
+                          void *stream, usv_vnn **out);
+/* all keys to ~0, frame numbering from 0 */
+usv_status usv_vnn_reset(usv_vnn *ctx);
+/* n frames (uint8, device, with pitches) at poses_host (FP64 4x4 each); frames whose pose
+ * is not finite or whose box misses the grid add nothing but keep their number */
+usv_status usv_vnn_ingest(usv_vnn *ctx, const uint8_t *frames_dev, int64_t row_pitch, int64_t frame_pitch,
+                          const double *poses_host, int32_t n);
+/* vol_u8_dev = value of the key (0 if not reached); state_dev (nullable) = 1 reached, 0 not */
+usv_status usv_vnn_finalize(usv_vnn *ctx, uint8_t *vol_u8_dev, uint8_t *state_dev);
+usv_status usv_vnn_destroy(usv_vnn *ctx);
+
+/* ---------------------------------------------------------------------------------
  * Batched multi-sweep ingest: n_sweeps independent (volume, probe, frames, poses)
  * jobs compounded by one persistent launch on the first volume's stream.  All
  * volumes must live on the same device.  Per sweep the result equals
@@ -324,6 +355,20 @@ usv_status usv_overlap_loss(usv_splat *ctx, const float *vols_dev, double *loss_
  * world point and J_l the SE(3) left Jacobian.  Weights are recomputed, not stored. */
 usv_status usv_splat_backward(usv_splat *ctx, const float *I_dev, const double *Tstar_dev, const double *xi_dev,
                               int32_t F, const float *grads_dev, float *dI_dev, double *dxi_dev);
+
+/* Distance-weighted (DW) compounding, the other comparison rule of the review cited in
+ * Sec. II.C, with the tent kernel of the splat above: each pixel of a uint8 frame spreads
+ * its value over its 8 nearest voxel centres with the trilinear weights w (geometry and
+ * dropping of out-of-grid corners as for the splat, T_n = poses_dev[n], the full
+ * image->world pose including any calibration); acc_dev FP32 [2][nvox] = (sum w I,
+ * sum w), accumulated over calls until usv_dw_clear.  usv_dw_finalize writes
+ * V = sum w I / sum w (FP32) where sum w >= w_min, else 0, and state 1 / 0 (nullable).
+ * Sums are FP32 atomics: the volume agrees with the FP64 definition to rounding, not bit
+ * for bit.  F <= max_frames per call; frames with pitches in bytes. */
+usv_status usv_dw_clear(usv_splat *ctx, float *acc_dev);
+usv_status usv_dw_ingest(usv_splat *ctx, const uint8_t *frames_dev, int64_t row_pitch, int64_t frame_pitch,
+                         const double *poses_dev, int32_t F, float *acc_dev);
+usv_status usv_dw_finalize(usv_splat *ctx, const float *acc_dev, float w_min, float *vol_dev, uint8_t *state_dev);
 
 /* Rigid patient motion between the two frame sets (motivated by Sec. III.A: the
  * patient moves between sweeps, so one sweep's tracked poses are off by one rigid

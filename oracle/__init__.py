@@ -42,6 +42,9 @@ def lib():
         L.orc_cut_rows_alg2.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                         C.c_int, C.c_int, P]
         L.orc_cut_rows_alg2.restype = None
+        L.orc_vnn.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_double, P, C.c_int, C.c_int, C.c_double, C.c_double,
+                              P, P, C.c_int, P, C.c_double, P, C.c_int64, P]
+        L.orc_vnn.restype = None
         L.orc_se3_exp.argtypes = [P, P]
         L.orc_se3_left_jacobian.argtypes = [P, P]
         L.orc_splat_forward.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_double, P, P, P, C.c_int, C.c_int,
@@ -145,6 +148,46 @@ def cut_rows_alg2(frames, y_lo=0, k=6, tau_I=128, tau_G=40, r=2, fallback_row=0,
     lib().orc_cut_rows_alg2(_p(frames), F, W, H, int(y_lo), int(k), int(tau_I), int(tau_G), int(r),
                             int(fallback_row), int(half_rows), _p(rows))
     return rows
+
+
+def vnn_keys(grid, frames, poses, probe, dmax_mm, calib=None, voxels=None):
+    """Voxel-nearest-neighbour keys (uint64: bits(d2) << 32 | frame << 8 | value, ~0 =
+    unreached) of all voxels ([nz][ny][nx]) or of the given flat voxel indices."""
+    calib = probe.calib if calib is None else calib
+    frames = _c(frames, np.uint8)
+    F, H, W = frames.shape
+    nx, ny, nz = grid.dims
+    mask = None if probe.mask is None else _c(probe.mask, np.uint8)
+    if voxels is None:
+        keys = np.empty(grid.nvox, dtype=np.uint64)
+        vp, nv = None, 0
+    else:
+        vox = _c(voxels, np.int64)
+        keys = np.empty(vox.size, dtype=np.uint64)
+        vp, nv = _p(vox), vox.size
+    lib().orc_vnn(nx, ny, nz, _p(_c(grid.origin_mm, np.float64)), float(grid.voxel_mm), _p(frames), W, H,
+                  float(probe.pixel_mm[0]), float(probe.pixel_mm[1]), _p(_c(poses, np.float64)),
+                  _p(_c(calib, np.float64)), F, _p(mask), float(dmax_mm), vp, nv, _p(keys))
+    return keys if voxels is not None else keys.reshape(nz, ny, nx)
+
+
+def vnn_volume(keys):
+    """(V uint8, state uint8: 1 reached / 0 not) from VNN keys."""
+    hit = keys != np.uint64(0xFFFFFFFFFFFFFFFF)
+    return np.where(hit, keys & np.uint64(0xFF), 0).astype(np.uint8), hit.astype(np.uint8)
+
+
+def dw_volume(grid, frames, poses, probe, w_min):
+    """Distance-weighted compounding with the trilinear (tent) kernel of the splat: every
+    frame's uint8 pixels spread over their 8 nearest voxel centres; V = sum w I / sum w
+    where sum w >= w_min (FP64).  Returns (V, sum w, state)."""
+    F = frames.shape[0]
+    I = _c(frames, np.uint8).astype(np.float32)
+    SA, WA, SB, WB = splat_forward(grid, I, poses, np.zeros((F, 6)), probe)
+    S, W = SA + SB, WA + WB
+    hit = (W >= w_min) & (W > 0)
+    V = np.where(hit, S / np.where(hit, W, 1.0), 0.0)
+    return V, W, hit.astype(np.uint8)
 
 
 def finalize(grid, sum_, cnt, fill_min=1):

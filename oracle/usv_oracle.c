@@ -17,6 +17,8 @@
  *     Steps 2-3 and the discussion of bone cortex over an acoustic shadow in Sec. II.D;
  *   - image-space cut (Img_C) of both algorithms before compounding: Table I Steps 4-6,
  *     Table II Steps 2-5;
+ *   - voxel-nearest-neighbour compounding, one of the rules compared in the review the
+ *     paper cites for its choice of PNN (Sec. II.C);
  *   - fixed-depth projection (VPI) baseline: Sec. I and Sec. III.B.
  * The differentiable trilinear splat, its loss and its gradient are not in the paper;
  * they follow the definitions written next to each routine.
@@ -386,6 +388,92 @@ void orc_cut_rows_alg2(const uint8_t *frames, int F, int W, int H, int y_lo, int
   free(win);
   free(col);
   free(c);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Voxel-nearest-neighbour compounding (a rule of the review cited in Sec. II.C), voxel
+ * by voxel.  For frame n, T = A_n C (products in index order, FP64), rotation columns
+ * R[:,m] = T[0..2][m], translation t = T[0..2][3].  Voxel (i, j, k) has centre
+ * c = o + s (i + 1/2, j + 1/2, k + 1/2); its image coordinates are
+ *   a = R[:,0].(c - t) / sx  (pixels along u),  b = R[:,1].(c - t) / sy,  h = R[:,2].(c - t)
+ * evaluated through a map rounded once to FP32: row m = (R[0][m] s, R[1][m] s, R[2][m] s,
+ * ((R[0][m] (o0 + s/2 - t0) + R[1][m] (o1 + s/2 - t1)) + R[2][m] (o2 + s/2 - t2))) / scale_m
+ * (FP64, scale = sx, sy, 1), then in FP32 q = (fl(N0 i) + fl(N1 j)) + (fl(N2 k) + N3).
+ * Frame n reaches the voxel iff 0 <= q_a < W, 0 <= q_b < H, |q_h| <= dmax (FP32) and
+ * the pixel (u, v) = (floor q_a, floor q_b) is inside the mask; its distance is
+ *   d2 = ((q_a - (u + 1/2)) sx)^2 + ((q_b - (v + 1/2)) sy)^2 + q_h^2  (FP32, in that order)
+ * (the squared distance from the voxel centre to the pixel centre, the pixel centre
+ * nearest to its projection).  The voxel takes the pixel of the smallest d2 over all
+ * frames, ties to the earlier frame: key = bits(d2) << 32 | n << 8 | value, minimised;
+ * ~0 when no frame reaches it.  vox: voxel indices to evaluate (NULL = all, nv ignored).
+ * ---------------------------------------------------------------------------------- */
+void orc_vnn(int nx, int ny, int nz, const double *origin, double s, const uint8_t *frames, int W, int H,
+             double sx, double sy, const double *poses, const double *C, int F, const uint8_t *mask, double dmax,
+             const int64_t *vox, int64_t nv, uint64_t *keys) {
+  float *N = (float *)malloc(sizeof(float) * 12 * (size_t)(F > 0 ? F : 1));
+  int *ok = (int *)malloc(sizeof(int) * (size_t)(F > 0 ? F : 1));
+  const double scale[3] = {sx, sy, 1.0};
+  for (int f = 0; f < F; ++f) {
+    const double *A = poses + 16 * f;
+    double T[16];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        double acc = A[r * 4 + 0] * C[0 * 4 + c];
+        acc = acc + A[r * 4 + 1] * C[1 * 4 + c];
+        acc = acc + A[r * 4 + 2] * C[2 * 4 + c];
+        acc = acc + A[r * 4 + 3] * C[3 * 4 + c];
+        T[r * 4 + c] = acc;
+      }
+    double off[3];
+    for (int r = 0; r < 3; ++r) off[r] = (origin[r] + 0.5 * s) - T[r * 4 + 3];
+    ok[f] = 1;
+    for (int m = 0; m < 3; ++m) {
+      for (int r = 0; r < 3; ++r) N[12 * f + 4 * m + r] = (float)((T[r * 4 + m] * s) / scale[m]);
+      double c = T[0 * 4 + m] * off[0];
+      c = c + T[1 * 4 + m] * off[1];
+      c = c + T[2 * 4 + m] * off[2];
+      N[12 * f + 4 * m + 3] = (float)(c / scale[m]);
+    }
+    for (int q = 0; q < 12; ++q)
+      if (!isfinite(N[12 * f + q])) ok[f] = 0;
+  }
+  const float Wf = (float)W, Hf = (float)H, fsx = (float)sx, fsy = (float)sy, fd = (float)dmax;
+  int64_t total = vox ? nv : (int64_t)nx * ny * nz;
+  for (int64_t e = 0; e < total; ++e) {
+    int64_t idx = vox ? vox[e] : e;
+    int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    float fi = (float)i, fj = (float)j, fk = (float)k;
+    uint64_t best = ~(uint64_t)0;
+    for (int f = 0; f < F; ++f) {
+      if (!ok[f]) continue;
+      const float *m = N + 12 * f;
+      float q[3];
+      for (int r = 0; r < 3; ++r) {
+        float t0 = m[4 * r] * fi;
+        float t1 = m[4 * r + 1] * fj;
+        float t2 = m[4 * r + 2] * fk;
+        float s01 = t0 + t1;
+        float s2 = t2 + m[4 * r + 3];
+        q[r] = s01 + s2;
+      }
+      if (!(q[0] >= 0.0f && q[0] < Wf && q[1] >= 0.0f && q[1] < Hf && fabsf(q[2]) <= fd)) continue;
+      int u = (int)q[0], v = (int)q[1];
+      if (mask && mask[(int64_t)v * W + u] == 0) continue;
+      float da = q[0] - ((float)u + 0.5f);
+      float db = q[1] - ((float)v + 0.5f);
+      float dA = da * fsx, dB = db * fsy;
+      float aa = dA * dA, bb = dB * dB, hh = q[2] * q[2];
+      float d2 = (aa + bb) + hh;
+      uint32_t bits;
+      memcpy(&bits, &d2, 4);
+      uint64_t key = ((uint64_t)bits << 32) | ((uint64_t)f << 8) |
+                     (uint64_t)frames[(int64_t)f * W * H + (int64_t)v * W + u];
+      if (key < best) best = key;
+    }
+    keys[e] = best;
+  }
+  free(ok);
+  free(N);
 }
 
 /* ------------------------------------------------------------------------------------

@@ -15,11 +15,12 @@ STATUS_NAMES = {0: "USV_OK", -1: "USV_E_ARG", -2: "USV_E_OOM", -3: "USV_E_DEVICE
 EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
-    "usv_ingest_frames", "usv_ingest_frames_cut", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
+    "usv_ingest_frames", "usv_ingest_frames_cut", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_vnn_create", "usv_vnn_reset", "usv_vnn_ingest",
+    "usv_vnn_finalize", "usv_vnn_destroy", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
     "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
     "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
-    "usv_splat_backward", "usv_refine_motion", "usv_fold_pose", "usv_dirty_box", "usv_version",
+    "usv_splat_backward", "usv_dw_clear", "usv_dw_ingest", "usv_dw_finalize", "usv_refine_motion", "usv_fold_pose", "usv_dirty_box", "usv_version",
 ]
 
 
@@ -95,6 +96,11 @@ def lib():
         "usv_ingest_frames": (I32, [P, I32, P, I64, I64, P, I32, C.POINTER(Box)]),
         "usv_ingest_frames_cut": (I32, [P, I32, P, I64, I64, P, P, I32, C.POINTER(Box)]),
         "usv_cut_rows_alg1": (I32, [C.POINTER(ProbeDesc), P, I32, C.POINTER(CutParams), P]),
+        "usv_vnn_create": (I32, [C.POINTER(GridDesc), C.POINTER(ProbeDesc), D, P, P, PP]),
+        "usv_vnn_reset": (I32, [P]),
+        "usv_vnn_ingest": (I32, [P, P, I64, I64, P, I32]),
+        "usv_vnn_finalize": (I32, [P, P, P]),
+        "usv_vnn_destroy": (I32, [P]),
         "usv_cut_rows_alg2": (I32, [P, I64, I64, I32, I32, I32, C.POINTER(CutParams), P, P, P]),
         "usv_finalize": (I32, [P, C.POINTER(Box), P, P]),
         "usv_segment_project": (I32, [P, C.POINTER(SegParams), P, P, P, P, P]),
@@ -116,6 +122,9 @@ def lib():
         "usv_splat_forward": (I32, [P, P, P, P, I32, P]),
         "usv_overlap_loss": (I32, [P, P, P, P]),
         "usv_splat_backward": (I32, [P, P, P, P, I32, P, P, P]),
+        "usv_dw_clear": (I32, [P, P]),
+        "usv_dw_ingest": (I32, [P, P, I64, I64, P, I32, P]),
+        "usv_dw_finalize": (I32, [P, P, C.c_float, P, P]),
         "usv_refine_motion": (I32, [P, P, P, I32, C.POINTER(RefineParams), P, P, P, P]),
         "usv_fold_pose": (I32, [C.POINTER(GridDesc), C.POINTER(ProbeDesc), P, P]),
         "usv_dirty_box": (I32, [C.POINTER(GridDesc), C.POINTER(ProbeDesc), P, I32, C.POINTER(Box)]),

@@ -1265,6 +1265,29 @@ usv_status usv_splat_backward(usv_splat *c, const float *I, const double *Tstar,
   return USV_OK;
 }
 
+usv_status usv_dw_clear(usv_splat *c, float *acc) {
+  if (!c || !acc) return USV_E_ARG;
+  return launch_zero_u32(reinterpret_cast<uint32_t *>(acc), 2 * c->nvox, c->stream) == hipSuccess ? USV_OK
+                                                                                                 : USV_E_DEVICE;
+}
+
+usv_status usv_dw_ingest(usv_splat *c, const uint8_t *frames, int64_t row_pitch, int64_t frame_pitch,
+                         const double *poses, int32_t F, float *acc) {
+  if (!c || F < 0 || F > c->max_frames || !acc || (F > 0 && (!frames || !poses))) return USV_E_ARG;
+  if (row_pitch < c->g.W || frame_pitch < 0 || (F > 1 && frame_pitch < (int64_t)(c->g.H - 1) * row_pitch + c->g.W))
+    return USV_E_ARG;
+  if (F == 0) return USV_OK;
+  if (launch_splat_pose(c->g, poses, nullptr, F, c->d_Mq, c->d_Jt, c->stream) != hipSuccess ||
+      launch_dw_ingest(c->g, frames, row_pitch, frame_pitch, c->d_Mq, F, acc, c->stream) != hipSuccess)
+    return USV_E_DEVICE;
+  return USV_OK;
+}
+
+usv_status usv_dw_finalize(usv_splat *c, const float *acc, float w_min, float *vol, uint8_t *state) {
+  if (!c || !acc || !vol || !(w_min >= 0.0f) || !std::isfinite(w_min)) return USV_E_ARG;
+  return launch_dw_finalize(c->nvox, acc, w_min, vol, state, c->stream) == hipSuccess ? USV_OK : USV_E_DEVICE;
+}
+
 usv_status usv_refine_motion(usv_splat *c, const float *I, const double *Tstar, int32_t F, const usv_refine_params *p,
                              double *xi, double *loss, float *vols, float *grads) {
   if (!c || !p || F < 1 || F > c->max_frames || !I || !Tstar || !xi || !loss || !vols || !grads) return USV_E_ARG;

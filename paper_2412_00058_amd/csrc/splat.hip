@@ -14,7 +14,10 @@
 //                          x dL/dq);
 //   frame_reduce_kernel  : per frame, sums the tile partials in tile order (deterministic)
 //                          and applies J_l^T;
-//   refine_step_kernel   : one Adam step on a rigid motion shared by the odd frames.
+//   refine_step_kernel   : one Adam step on a rigid motion shared by the odd frames;
+//   dw_finalize_kernel   : the distance-weighted (tent kernel) compounding's S / W.
+#include <algorithm>
+
 #include "usv_internal.h"
 
 namespace usv {
@@ -38,7 +41,9 @@ __global__ __launch_bounds__(64) void splat_pose_kernel(SplatGeom g, const doubl
   __shared__ double ad[36], Pk[2][36];
   const int n = blockIdx.x;
   const int t = threadIdx.x;
-  const double *x = xi + 6 * n;
+  double x[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // null xi: T = T* exactly
+  if (xi)
+    for (int q = 0; q < 6; ++q) x[q] = xi[6 * n + q];
   const double w0 = x[3], w1 = x[4], w2 = x[5];
   const double W[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
   if (t == 0) {
@@ -148,8 +153,12 @@ __device__ __forceinline__ void pixel_coord(const double *m, int u, int v, const
 // 2^-(52 - e) units where 2^e bounds |I| over the tile, so no sum can reach 2^62 and each
 // contribution is rounded by at most 2^-53 of the tile's largest |I|.  The window is
 // flushed with FP32 global atomics of the converted sums.
-__global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float *__restrict__ I,
-                                                        const double *__restrict__ Mq, float *__restrict__ vols) {
+// kU8: uint8 intensities with pitches (distance-weighted compounding); one_set: every
+// frame feeds the first (S, W) pair instead of the even / odd split.
+template <bool kU8>
+__global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void *__restrict__ Iv, int64_t row_pitch,
+                                                        int64_t frame_pitch, const double *__restrict__ Mq,
+                                                        float *__restrict__ vols, int one_set) {
   __shared__ __align__(16) unsigned long long win[2 * kSplatWin];   // (S, W) of entry e at 2e, 2e + 1
   __shared__ float red[4];
   const int b = blockIdx.x;
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float
   const bool direct = we64 > kSplatWin;
   const int we = direct ? 0 : (int)we64;
   const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
-  float *S = vols + (int64_t)(f & 1) * 2 * nvox;
+  float *S = vols + (one_set ? (int64_t)0 : (int64_t)(f & 1) * 2 * nvox);
   float *Wt = S + nvox;
   const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
   const int u = u0 + tx;
@@ -180,7 +189,11 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const float
 #pragma unroll
   for (int k = 0; k < STH / 8; ++k) {
     const int v = v0 + ty0 + 8 * k;
-    val[k] = (u <= u1 && v <= v1) ? I[((int64_t)f * g.H + v) * g.W + u] : 0.0f;
+    const int64_t pix = (int64_t)f * frame_pitch + (int64_t)v * row_pitch + u;
+    if (kU8)
+      val[k] = (u <= u1 && v <= v1) ? (float)static_cast<const uint8_t *>(Iv)[pix] : 0.0f;
+    else
+      val[k] = (u <= u1 && v <= v1) ? static_cast<const float *>(Iv)[pix] : 0.0f;
     amax = fmaxf(amax, fabsf(val[k]));
   }
   for (int e = threadIdx.x; e < 2 * we; e += 256) win[e] = 0ull;
@@ -461,6 +474,17 @@ __global__ void refine_step_kernel(const double *__restrict__ dxi, int F, int t,
   }
 }
 
+// Distance-weighted volume: V = S / W where W >= w_min (state 1), else 0 (state 0).
+__global__ void dw_finalize_kernel(int64_t nvox, const float *__restrict__ acc, float w_min, float *__restrict__ V,
+                                   uint8_t *__restrict__ state) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox; i += (int64_t)gridDim.x * blockDim.x) {
+    const float S = acc[i], W = acc[nvox + i];
+    const bool hit = W >= w_min && W > 0.0f;
+    V[i] = hit ? S / W : 0.0f;
+    if (state) state[i] = hit ? (uint8_t)1 : (uint8_t)0;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_splat_pose(const SplatGeom &g, const double *Tstar, const double *xi, int F, double *Mq, double *Jt,
@@ -476,7 +500,23 @@ hipError_t launch_splat_forward(const SplatGeom &g, const float *I, const double
   hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(vols), 4 * nvox, s);
   if (e != hipSuccess || F <= 0) return e;
   const int blocks = F * g.tiles_x * g.tiles_y;
-  hipLaunchKernelGGL(splat_fwd_kernel, dim3(blocks), dim3(256), 0, s, g, I, Mq, vols);
+  hipLaunchKernelGGL(splat_fwd_kernel<false>, dim3(blocks), dim3(256), 0, s, g, (const void *)I, (int64_t)g.W,
+                     (int64_t)g.W * g.H, Mq, vols, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dw_ingest(const SplatGeom &g, const uint8_t *I, int64_t row_pitch, int64_t frame_pitch,
+                            const double *Mq, int F, float *acc, hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  const int blocks = F * g.tiles_x * g.tiles_y;
+  hipLaunchKernelGGL(splat_fwd_kernel<true>, dim3(blocks), dim3(256), 0, s, g, (const void *)I, row_pitch,
+                     frame_pitch, Mq, acc, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_dw_finalize(int64_t nvox, const float *acc, float w_min, float *V, uint8_t *state, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((nvox + 255) / 256, 65536);
+  hipLaunchKernelGGL(dw_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nvox, acc, w_min, V, state);
   return hipGetLastError();
 }
 

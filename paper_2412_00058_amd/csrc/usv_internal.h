@@ -153,6 +153,12 @@ hipError_t launch_overlap_loss(int64_t nvox, const float *vols, float *grads, do
 hipError_t launch_splat_backward(const SplatGeom &g, const float *I, const double *Mq, const double *Jt, int F,
                                  const float *grads, float *dI, double *partial, double *dxi, hipStream_t s);
 
+// distance-weighted compounding: the forward splat of uint8 frames (pitched) into one
+// (S, W) pair, accumulated; then V = S / W where W >= w_min
+hipError_t launch_dw_ingest(const SplatGeom &g, const uint8_t *I, int64_t row_pitch, int64_t frame_pitch,
+                            const double *Mq, int F, float *acc, hipStream_t s);
+hipError_t launch_dw_finalize(int64_t nvox, const float *acc, float w_min, float *V, uint8_t *state, hipStream_t s);
+
 struct RefineAdam {
   double lr_rho, lr_omega, beta1, beta2, eps;
 };

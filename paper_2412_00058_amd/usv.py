@@ -367,6 +367,52 @@ def version() -> str:
 # --- differentiable splat -------------------------------------------------------------------
 
 
+class VNN:
+    """Voxel-nearest-neighbour compounding into its own 8-byte key per voxel (comparison
+    rule beside the PNN Volume), on the current torch stream."""
+
+    def __init__(self, dims, origin_mm, voxel_mm, width, height, pixel_mm, dmax_mm, calib=None, mask=None,
+                 device="cuda"):
+        self.dims = tuple(int(d) for d in dims)
+        nvox = self.dims[0] * self.dims[1] * self.dims[2]
+        self.keys = torch.empty(nvox, dtype=torch.int64, device=device)
+        g = grid_desc(dims, origin_mm, voxel_mm)
+        pd, keep = probe_desc(width, height, pixel_mm, calib, mask)
+        h = C.c_void_p()
+        check(lib().usv_vnn_create(C.byref(g), C.byref(pd), float(dmax_mm), _vp(self.keys), _stream_ptr(),
+                                   C.byref(h)))
+        del keep
+        self.h = h
+
+    def reset(self):
+        check(lib().usv_vnn_reset(self.h))
+
+    def ingest(self, frames: torch.Tensor, poses):
+        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3 and frames.stride(2) == 1
+        P = _poses(poses)
+        assert P.shape[0] == frames.shape[0]
+        check(lib().usv_vnn_ingest(self.h, _vp(frames), frames.stride(1), frames.stride(0),
+                                   P.ctypes.data_as(C.c_void_p), frames.shape[0]))
+
+    def finalize(self, with_state=True):
+        nx, ny, nz = self.dims
+        V = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.keys.device)
+        S = torch.empty_like(V) if with_state else None
+        check(lib().usv_vnn_finalize(self.h, _vp(V), _vp(S)))
+        return V, S
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().usv_vnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class SplatContext:
     """Geometry + scratch of the trilinear splat on the current torch stream."""
 
@@ -398,6 +444,28 @@ class SplatContext:
         dxi = torch.empty((F, 6), dtype=torch.float64, device=I.device) if dxi is None else dxi
         check(lib().usv_splat_backward(self.h, _vp(I), _vp(Tstar), _vp(xi), F, _vp(grads), _vp(dI), _vp(dxi)))
         return dI, dxi
+
+    def dw_clear(self, acc=None):
+        """(Re)zeroed distance-weighted accumulator FP32 [2, nvox] (sum w I, sum w)."""
+        if acc is None:
+            acc = torch.empty((2, self.nvox), dtype=torch.float32, device="cuda")
+        check(lib().usv_dw_clear(self.h, _vp(acc)))
+        return acc
+
+    def dw_ingest(self, acc, frames: torch.Tensor, poses_dev: torch.Tensor):
+        """Distance-weighted compounding of uint8 frames [F, H, W] (device) at image->world
+        poses (FP64 device [F, 4, 4]) into acc."""
+        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3 and frames.stride(2) == 1
+        P = poses_dev.contiguous()
+        check(lib().usv_dw_ingest(self.h, _vp(frames), frames.stride(1), frames.stride(0), _vp(P), frames.shape[0],
+                                  _vp(acc)))
+
+    def dw_finalize(self, acc, w_min=0.05):
+        nx, ny, nz = self.dims
+        V = torch.empty((nz, ny, nx), dtype=torch.float32, device=acc.device)
+        S = torch.empty((nz, ny, nx), dtype=torch.uint8, device=acc.device)
+        check(lib().usv_dw_finalize(self.h, _vp(acc), C.c_float(w_min), _vp(V), _vp(S)))
+        return V, S
 
     def refine_motion(self, I, Tstar, xi0=None, iters=150, lr_rho=0.05, lr_omega=math.radians(0.05), beta1=0.9,
                       beta2=0.999, eps=1e-8, vols=None, grads=None):
