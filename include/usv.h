@@ -395,6 +395,18 @@ usv_status usv_refine_motion(usv_splat *ctx, const float *I_dev, const double *T
                              float *grads_dev);
 
 /* ---------------------------------------------------------------------------------
+ * Slice export (Sec. II.C: the finished volume is written out as 2-D slices along the
+ * spine axis).  Slices first .. first+count-1 perpendicular to `axis` of the uint8
+ * volume vol_dev [nz][ny][nx] (dims = nx, ny, nz) go to out_dev, count slices back to
+ * back, each keeping the other two axes in storage order with the slower one as rows:
+ * axis 2 -> [ny][nx], axis 1 -> [nz][nx], axis 0 -> [nz][ny].  Ordered on `stream`.
+ * USV_E_ARG for a range outside the axis; USV_E_UNSUPPORTED for axes 0 and 1 with
+ * nz > 65535.
+ * --------------------------------------------------------------------------------- */
+usv_status usv_extract_slices(const uint8_t *vol_dev, const int32_t dims[3], int32_t axis, int32_t first,
+                              int32_t count, uint8_t *out_dev, void *stream);
+
+/* ---------------------------------------------------------------------------------
  * Host-only helpers (no device work; usable without a GPU)
  * --------------------------------------------------------------------------------- */
 

@@ -16,7 +16,7 @@ EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
     "usv_ingest_frames", "usv_ingest_frames_cut", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_vnn_create", "usv_vnn_reset", "usv_vnn_ingest",
-    "usv_vnn_finalize", "usv_vnn_destroy", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
+    "usv_vnn_finalize", "usv_vnn_destroy", "usv_extract_slices", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
     "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
     "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
@@ -96,6 +96,7 @@ def lib():
         "usv_ingest_frames": (I32, [P, I32, P, I64, I64, P, I32, C.POINTER(Box)]),
         "usv_ingest_frames_cut": (I32, [P, I32, P, I64, I64, P, P, I32, C.POINTER(Box)]),
         "usv_cut_rows_alg1": (I32, [C.POINTER(ProbeDesc), P, I32, C.POINTER(CutParams), P]),
+        "usv_extract_slices": (I32, [P, C.POINTER(C.c_int32 * 3), I32, I32, I32, P, P]),
         "usv_vnn_create": (I32, [C.POINTER(GridDesc), C.POINTER(ProbeDesc), D, P, P, PP]),
         "usv_vnn_reset": (I32, [P]),
         "usv_vnn_ingest": (I32, [P, P, I64, I64, P, I32]),

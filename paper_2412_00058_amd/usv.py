@@ -95,6 +95,39 @@ def cut_rows_alg2(frames: torch.Tensor, params: CutParams, scratch=None, rows=No
     return rows
 
 
+def extract_slices(V: torch.Tensor, axis: int = 2, first: int = 0, count: Optional[int] = None) -> torch.Tensor:
+    """Slices of a uint8 device volume [nz, ny, nx] perpendicular to `axis` (2 = z, the
+    spine axis of the sweeps here), on the device: [count, rows, cols]."""
+    assert V.dtype == torch.uint8 and V.is_cuda and V.dim() == 3 and V.is_contiguous()
+    nz, ny, nx = V.shape
+    n_axis = (nx, ny, nz)[axis]
+    count = n_axis - first if count is None else count
+    shape = {2: (ny, nx), 1: (nz, nx), 0: (nz, ny)}[axis]
+    out = torch.empty((max(count, 0),) + shape, dtype=torch.uint8, device=V.device)
+    dims = (C.c_int32 * 3)(nx, ny, nz)
+    check(lib().usv_extract_slices(_vp(V), C.byref(dims), int(axis), int(first), int(count), _vp(out),
+                                   _stream_ptr()))
+    return out
+
+
+def export_slices(V: torch.Tensor, directory: str, axis: int = 2, prefix: str = "slice", first: int = 0,
+                  count: Optional[int] = None) -> list:
+    """Write the slices as binary PGM images (P5, 8-bit) prefix_NNNNN.pgm in `directory`,
+    numbered by their index along the axis; returns the paths."""
+    import os
+    sl = extract_slices(V, axis, first, count).cpu().numpy()
+    os.makedirs(directory, exist_ok=True)
+    paths = []
+    for c in range(sl.shape[0]):
+        path = os.path.join(directory, "%s_%05d.pgm" % (prefix, first + c))
+        rows, cols = sl.shape[1], sl.shape[2]
+        with open(path, "wb") as fh:
+            fh.write(b"P5\n%d %d\n255\n" % (cols, rows))
+            fh.write(np.ascontiguousarray(sl[c]).tobytes())
+        paths.append(path)
+    return paths
+
+
 def _poses(poses) -> np.ndarray:
     a = np.ascontiguousarray(poses, dtype=np.float64)
     return a.reshape(-1, 16)

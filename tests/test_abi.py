@@ -118,3 +118,25 @@ def test_dirty_box_skips_nonfinite_and_rejects_huge_poses():
     A[0, 3] = 1e30
     with pytest.raises(_lib.UsvError):
         U.dirty_box((8, 8, 8), (0, 0, 0), 0.5, 4, 4, (0.1, 0.1), None, A[None])
+
+
+def test_slice_and_cut_argument_validation():
+    """Host-side checks of the export and cut entry points (no device work is issued)."""
+    L = _lib.lib()
+    dims = (C.c_int32 * 3)(8, 6, 4)
+    E = _lib.USV_E_ARG
+    assert L.usv_extract_slices(None, C.byref(dims), 3, 0, 1, None, None) == E          # axis
+    assert L.usv_extract_slices(None, C.byref(dims), 0, 5, 4, None, None) == E          # past the end
+    assert L.usv_extract_slices(None, C.byref(dims), 2, -1, 1, None, None) == E
+    assert L.usv_extract_slices(None, C.byref(dims), 2, 4, 0, None, None) == _lib.USV_OK  # empty range
+    assert L.usv_extract_slices(None, C.byref(dims), 2, 0, 1, None, None) == E          # null volume
+    prm = U.cut_params(k=0)
+    assert L.usv_cut_rows_alg2(None, 8, 48, 2, 8, 6, C.byref(prm), None, None, None) == E
+    prm = U.cut_params(fallback_row=6)
+    assert L.usv_cut_rows_alg2(None, 8, 48, 2, 8, 6, C.byref(prm), None, None, None) == E
+    prm = U.cut_params()
+    assert L.usv_cut_rows_alg2(None, 8, 48, 0, 8, 6, C.byref(prm), None, None, None) == _lib.USV_OK
+    assert L.usv_ingest_frames_cut(None, 0, None, 0, 0, None, None, 0, None) == E
+    assert L.usv_vnn_ingest(None, None, 0, 0, None, 0) == E
+    assert L.usv_dw_ingest(None, None, 0, 0, None, 0, None) == E
+    assert L.usv_refine_motion(None, None, None, 0, None, None, None, None, None) == E
