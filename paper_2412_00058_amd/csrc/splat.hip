@@ -12,11 +12,12 @@
 //   splat_bwd_kernel     : recomputes the weights, gathers the gradient volumes, writes
 //                          dL/dI and a per-tile FP64 partial of (sum dL/dq, sum (p - p_c)
 //                          x dL/dq);
-//   frame_reduce_kernel  : per frame, sums the tile partials in tile order (deterministic)
-//                          and applies J_l^T;
+//   frame_reduce_kernel  : one wave per frame sums the tile partials in a fixed order
+//                          (deterministic) and applies J_l^T;
 //   refine_step_kernel   : one Adam step on a rigid motion shared by the odd frames;
 //   dw_finalize_kernel   : the distance-weighted (tent kernel) compounding's S / W.
 #include <algorithm>
+#include <cmath>
 
 #include "usv_internal.h"
 
@@ -147,19 +148,19 @@ __device__ __forceinline__ void pixel_coord(const double *m, int u, int v, const
   }
 }
 
-// Forward splat of one 32x32 pixel tile.  Contributions are merged in the LDS window as
+// Forward splat of one 32x32 pixel tile.  Contributions are merged in an LDS window as
 // 64-bit fixed-point integers (integer LDS atomics are several times faster than FP32
-// ones on gfx950): W with 2^-52 units (a voxel takes at most 1024 weights <= 1), S with
-// 2^-(52 - e) units where 2^e bounds |I| over the tile, so no sum can reach 2^62 and each
-// contribution is rounded by at most 2^-53 of the tile's largest |I|.  The window is
-// flushed with FP32 global atomics of the converted sums.
-// kU8: uint8 intensities with pitches (distance-weighted compounding); one_set: every
-// frame feeds the first (S, W) pair instead of the even / odd split.
+// ones on gfx950): each term is rounded to a 32-bit integer -- W in 2^-30 units, S in
+// 2^-(30 - e) units where 2^e bounds |I| over the tile -- so a term converts with one
+// instruction and no window sum can reach 2^41; each term is rounded by at most 2^-31 of
+// its bound.  The window (dynamic LDS, win_cap entries, sized by the host from the
+// tile's largest possible voxel box) is flushed with FP32 global atomics of the
+// converted sums.
 template <bool kU8>
 __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void *__restrict__ Iv, int64_t row_pitch,
                                                         int64_t frame_pitch, const double *__restrict__ Mq,
-                                                        float *__restrict__ vols, int one_set) {
-  __shared__ __align__(16) unsigned long long win[2 * kSplatWin];   // (S, W) of entry e at 2e, 2e + 1
+                                                        float *__restrict__ vols, int one_set, int win_cap) {
+  extern __shared__ __align__(16) unsigned long long win[];   // (S, W) of entry e at 2e, 2e + 1
   __shared__ float red[4];
   const int b = blockIdx.x;
   const int tc = b % g.tiles_x, rest = b / g.tiles_x;
@@ -176,25 +177,26 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
   if (!splat_axis(m + 6, du0, du1, dv0, dv1, g.nz, lo[2], hi[2])) return;
   const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
   const int64_t we64 = (int64_t)wx * wy * wz;
-  const bool direct = we64 > kSplatWin;
+  const bool direct = we64 > win_cap;
   const int we = direct ? 0 : (int)we64;
   const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
   float *S = vols + (one_set ? (int64_t)0 : (int64_t)(f & 1) * 2 * nvox);
   float *Wt = S + nvox;
-  const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
-  const int u = u0 + tx;
-  // this lane's four pixels, and the tile's largest |I|
-  float val[STH / 8];
+  // this lane's pixels: a run of four along one row (lanes 8 r .. 8 r + 7 cover row r),
+  // and the tile's largest |I|
+  const int u_run = u0 + 4 * (threadIdx.x & 7), v = v0 + (threadIdx.x >> 3);
+  float val[4];
   float amax = 0.0f;
+  const int64_t rowpix = (int64_t)f * frame_pitch + (int64_t)v * row_pitch;
 #pragma unroll
-  for (int k = 0; k < STH / 8; ++k) {
-    const int v = v0 + ty0 + 8 * k;
-    const int64_t pix = (int64_t)f * frame_pitch + (int64_t)v * row_pitch + u;
+  for (int j = 0; j < 4; ++j) {
+    const int u = u_run + j;
+    const bool in = u <= u1 && v <= v1;
     if (kU8)
-      val[k] = (u <= u1 && v <= v1) ? (float)static_cast<const uint8_t *>(Iv)[pix] : 0.0f;
+      val[j] = in ? (float)static_cast<const uint8_t *>(Iv)[rowpix + u] : 0.0f;
     else
-      val[k] = (u <= u1 && v <= v1) ? static_cast<const float *>(Iv)[pix] : 0.0f;
-    amax = fmaxf(amax, fabsf(val[k]));
+      val[j] = in ? static_cast<const float *>(Iv)[rowpix + u] : 0.0f;
+    amax = fmaxf(amax, fabsf(val[j]));
   }
   for (int e = threadIdx.x; e < 2 * we; e += 256) win[e] = 0ull;
 #pragma unroll
@@ -204,35 +206,79 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
   amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   int ex = 0;
   if (amax > 0.0f && amax <= 3.0e38f) (void)frexpf(amax, &ex);   // |I| < 2^ex
-  const int ks = min(127, max(-126, 52 - ex));   // scale exponent of S (a normal float)
-  const float sc_s = ldexpf(1.0f, ks), sc_w = ldexpf(1.0f, 52);
+  const int ks = min(127, max(-126, 30 - ex));   // scale exponent of S (a normal float)
+  const float sc_s = ldexpf(1.0f, ks), sc_w = ldexpf(1.0f, 30);
+  if (direct) {
 #pragma unroll
-  for (int k = 0; k < STH / 8; ++k) {
-    const int v = v0 + ty0 + 8 * k;
-    if (u > u1 || v > v1) continue;
-    PixW p;
-    double pd[3];
-    pixel_coord(m, u, v, g, p, pd);
+    for (int j = 0; j < 4; ++j) {
+      const int u = u_run + j;
+      if (u > u1 || v > v1) continue;
+      PixW p;
+      double pd[3];
+      pixel_coord(m, u, v, g, p, pd);
 #pragma unroll
-    for (int dlt = 0; dlt < 8; ++dlt) {
-      const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
-      if (!(bx ? p.ok1[0] : p.ok0[0]) || !(by ? p.ok1[1] : p.ok0[1]) || !(bz ? p.ok1[2] : p.ok0[2])) continue;
-      const float w = (bx ? p.f[0] : 1.0f - p.f[0]) * (by ? p.f[1] : 1.0f - p.f[1]) * (bz ? p.f[2] : 1.0f - p.f[2]);
-      const int cx = p.i0[0] + bx, cy = p.i0[1] + by, cz = p.i0[2] + bz;
-      if (!direct) {
-        const int e = (cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2]));
-        atomicAdd(&win[2 * e], (unsigned long long)__float2ll_rn((w * val[k]) * sc_s));
-        atomicAdd(&win[2 * e + 1], (unsigned long long)__float2ll_rn(w * sc_w));
-      } else {
-        const int64_t gi = (int64_t)cx + (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
-        atomicAdd(S + gi, w * val[k]);
+      for (int dlt = 0; dlt < 8; ++dlt) {
+        const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+        if (!(bx ? p.ok1[0] : p.ok0[0]) || !(by ? p.ok1[1] : p.ok0[1]) || !(bz ? p.ok1[2] : p.ok0[2])) continue;
+        const float w = (bx ? p.f[0] : 1.0f - p.f[0]) * (by ? p.f[1] : 1.0f - p.f[1]) * (bz ? p.f[2] : 1.0f - p.f[2]);
+        const int64_t gi = (int64_t)(p.i0[0] + bx) + (int64_t)g.nx * ((int64_t)(p.i0[1] + by) + (int64_t)g.ny * (p.i0[2] + bz));
+        atomicAdd(S + gi, w * val[j]);
         atomicAdd(Wt + gi, w);
       }
     }
+  } else {
+    // consecutive pixels of the run that share their base voxel add their fixed-point
+    // terms in registers (integer sums: the same totals as one LDS atomic per term) and
+    // reach the window once per base voxel
+    long long aS[8], aW[8];
+    int c0 = 0, c1 = 0, c2 = 0;
+    uint32_t okm = 0u;   // bit d: corner d inside the grid
+    bool open = false;
+    auto flush = [&]() {
+#pragma unroll
+      for (int dlt = 0; dlt < 8; ++dlt) {
+        if (!(okm & (1u << dlt))) continue;
+        const int e = (c0 + (dlt & 1) - lo[0]) + wx * ((c1 + ((dlt >> 1) & 1) - lo[1]) + wy * (c2 + (dlt >> 2) - lo[2]));
+        atomicAdd(&win[2 * e], (unsigned long long)aS[dlt]);
+        atomicAdd(&win[2 * e + 1], (unsigned long long)aW[dlt]);
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int u = u_run + j;
+      if (u > u1 || v > v1) continue;
+      PixW p;
+      double pd[3];
+      pixel_coord(m, u, v, g, p, pd);
+      if (!open || p.i0[0] != c0 || p.i0[1] != c1 || p.i0[2] != c2) {
+        if (open) flush();
+        open = true;
+        c0 = p.i0[0];
+        c1 = p.i0[1];
+        c2 = p.i0[2];
+        okm = 0u;
+#pragma unroll
+        for (int dlt = 0; dlt < 8; ++dlt) {
+          const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+          const bool ok = (bx ? p.ok1[0] : p.ok0[0]) && (by ? p.ok1[1] : p.ok0[1]) && (bz ? p.ok1[2] : p.ok0[2]);
+          okm |= ok ? (1u << dlt) : 0u;
+          aS[dlt] = 0;
+          aW[dlt] = 0;
+        }
+      }
+#pragma unroll
+      for (int dlt = 0; dlt < 8; ++dlt) {
+        const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+        const float w = (bx ? p.f[0] : 1.0f - p.f[0]) * (by ? p.f[1] : 1.0f - p.f[1]) * (bz ? p.f[2] : 1.0f - p.f[2]);
+        aS[dlt] += (long long)__float2int_rn((w * val[j]) * sc_s);
+        aW[dlt] += (long long)__float2int_rn(w * sc_w);
+      }
+    }
+    if (open) flush();
   }
   __syncthreads();
   if (direct) return;
-  const double inv_s = ldexp(1.0, -ks), inv_w = ldexp(1.0, -52);
+  const double inv_s = ldexp(1.0, -ks), inv_w = ldexp(1.0, -30);
   const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
   for (int e = threadIdx.x; e < we; e += 256) {
     const ulonglong2 sw = *reinterpret_cast<const ulonglong2 *>(&win[2 * e]);
@@ -403,21 +449,26 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   }
 }
 
-__global__ void frame_reduce_kernel(SplatGeom g, const double *__restrict__ Mq, const double *__restrict__ Jt,
-                                    const double *__restrict__ partial, int F, double *__restrict__ dxi) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= F) return;
+// One wave per frame: lane l sums tiles l, l + 64, ... in order, the 64 lane sums are
+// combined by a fixed butterfly (deterministic), then lane 0 applies J_l^T.
+__global__ __launch_bounds__(64) void frame_reduce_kernel(SplatGeom g, const double *__restrict__ Mq,
+                                                          const double *__restrict__ Jt,
+                                                          const double *__restrict__ partial, int F,
+                                                          double *__restrict__ dxi) {
+  const int f = blockIdx.x;
+  const int lane = threadIdx.x;
   const int tiles = g.tiles_x * g.tiles_y;
-  double sg[3] = {0, 0, 0}, sm[3] = {0, 0, 0};
-  for (int t = 0; t < tiles; ++t) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = lane; t < tiles; t += 64) {
     const double *p = partial + ((int64_t)f * tiles + t) * 6;
-    sg[0] += p[0];
-    sg[1] += p[1];
-    sg[2] += p[2];
-    sm[0] += p[3];
-    sm[1] += p[4];
-    sm[2] += p[5];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] += p[k];
   }
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+  if (lane != 0) return;
+  const double sg[3] = {acc[0], acc[1], acc[2]}, sm[3] = {acc[3], acc[4], acc[5]};
   const double *m = Mq + 9 * f;
   const double uc = 0.5 * (double)(g.W - 1), vc = 0.5 * (double)(g.H - 1);
   double c[3], gx[3];
@@ -430,32 +481,48 @@ __global__ void frame_reduce_kernel(SplatGeom g, const double *__restrict__ Mq, 
                   sm[2] + c[0] * gx[1] - c[1] * gx[0]};
   const double *J = Jt + 36 * f;
   for (int i = 0; i < 6; ++i) {
-    double acc = 0.0;
-    for (int j = 0; j < 6; ++j) acc += J[i * 6 + j] * de[j];
-    dxi[6 * f + i] = acc;
+    double v = 0.0;
+    for (int j = 0; j < 6; ++j) v += J[i * 6 + j] * de[j];
+    dxi[6 * f + i] = v;
   }
 }
 
 // One Adam step on the shared motion xi of the odd frames (the moving frame set): the
 // motion gradient is the sum of the per-frame gradients dL/dxi_n over odd n (each odd
-// frame's pose is Exp(xi) T*_n, so d xi_n / d xi = identity), summed in frame order.
+// frame's pose is Exp(xi) T*_n, so d xi_n / d xi = identity), summed in a fixed order.
 // Adam (Kingma and Ba, 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
 // xi -= lr m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps), lr per component (translation in mm,
 // rotation in rad).  t = 0 only initialises m, v = 0.  Then every frame's perturbation
-// is rewritten: xi for odd frames, 0 for even frames.  One block of 64 threads.
-__global__ void refine_step_kernel(const double *__restrict__ dxi, int F, int t, RefineAdam a,
-                                   double *__restrict__ state, double *__restrict__ xi_frames) {
+// is rewritten: xi for odd frames, 0 for even frames.  One block of 256 threads.
+__global__ __launch_bounds__(256) void refine_step_kernel(const double *__restrict__ dxi, int F, int t, RefineAdam a,
+                                                          double *__restrict__ state,
+                                                          double *__restrict__ xi_frames) {
   // state: xi[6], m[6], v[6]
+  __shared__ double red[6][4];
   __shared__ double xs[6];
-  const int k = threadIdx.x;
-  if (k < 6) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (t > 0) {
+    // thread tid sums odd frames 2 (tid + 256 j) + 1 in order; lanes, then waves, combine
+    // in a fixed order
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    for (int n = 2 * tid + 1; n < F; n += 512)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) g[k] += dxi[6 * n + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      for (int o = 32; o > 0; o >>= 1) g[k] += __shfl_xor(g[k], o);
+      if (lane == 0) red[k][wv] = g[k];
+    }
+  }
+  __syncthreads();
+  if (tid < 6) {
+    const int k = tid;
     double x = state[k];
     if (t == 0) {
       state[6 + k] = 0.0;
       state[12 + k] = 0.0;
     } else {
-      double gsum = 0.0;
-      for (int n = 1; n < F; n += 2) gsum += dxi[6 * n + k];
+      const double gsum = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
       const double m = a.beta1 * state[6 + k] + (1.0 - a.beta1) * gsum;
       const double v = a.beta2 * state[12 + k] + (1.0 - a.beta2) * gsum * gsum;
       state[6 + k] = m;
@@ -468,7 +535,7 @@ __global__ void refine_step_kernel(const double *__restrict__ dxi, int F, int t,
     xs[k] = x;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 6 * F; e += 64) {
+  for (int e = tid; e < 6 * F; e += 256) {
     const int n = e / 6;
     xi_frames[e] = (n & 1) ? xs[e - 6 * n] : 0.0;
   }
@@ -483,6 +550,18 @@ __global__ void dw_finalize_kernel(int64_t nvox, const float *__restrict__ acc, 
     V[i] = hit ? S / W : 0.0f;
     if (state) state[i] = hit ? (uint8_t)1 : (uint8_t)0;
   }
+}
+
+// LDS window entries a forward block needs at most: the pixel centres of a tile span
+// ((STW-1) sx, (STH-1) sy) mm, so along every axis the voxel box of a tile is at most
+// floor(d) + 3 voxels wide for d = that diagonal in voxels, whatever the pose; capped at
+// kSplatWin (tiles beyond the cap take the direct path).
+int splat_window_cap(const SplatGeom &g) {
+  const double a = (STW - 1) * g.sx, b = (STH - 1) * g.sy;
+  const double d = std::sqrt(a * a + b * b) / g.s;
+  if (!(d < 64.0)) return kSplatWin;
+  const int e = (int)std::floor(d) + 3;
+  return std::min<int>(kSplatWin, e * e * e);
 }
 
 }  // namespace
@@ -500,8 +579,9 @@ hipError_t launch_splat_forward(const SplatGeom &g, const float *I, const double
   hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(vols), 4 * nvox, s);
   if (e != hipSuccess || F <= 0) return e;
   const int blocks = F * g.tiles_x * g.tiles_y;
-  hipLaunchKernelGGL(splat_fwd_kernel<false>, dim3(blocks), dim3(256), 0, s, g, (const void *)I, (int64_t)g.W,
-                     (int64_t)g.W * g.H, Mq, vols, 0);
+  const int cap = splat_window_cap(g);
+  hipLaunchKernelGGL(splat_fwd_kernel<false>, dim3(blocks), dim3(256), (size_t)cap * 16, s, g, (const void *)I,
+                     (int64_t)g.W, (int64_t)g.W * g.H, Mq, vols, 0, cap);
   return hipGetLastError();
 }
 
@@ -509,8 +589,9 @@ hipError_t launch_dw_ingest(const SplatGeom &g, const uint8_t *I, int64_t row_pi
                             const double *Mq, int F, float *acc, hipStream_t s) {
   if (F <= 0) return hipSuccess;
   const int blocks = F * g.tiles_x * g.tiles_y;
-  hipLaunchKernelGGL(splat_fwd_kernel<true>, dim3(blocks), dim3(256), 0, s, g, (const void *)I, row_pitch,
-                     frame_pitch, Mq, acc, 1);
+  const int cap = splat_window_cap(g);
+  hipLaunchKernelGGL(splat_fwd_kernel<true>, dim3(blocks), dim3(256), (size_t)cap * 16, s, g, (const void *)I,
+                     row_pitch, frame_pitch, Mq, acc, 1, cap);
   return hipGetLastError();
 }
 
@@ -536,13 +617,13 @@ hipError_t launch_splat_backward(const SplatGeom &g, const float *I, const doubl
   hipLaunchKernelGGL(splat_bwd_kernel, dim3(blocks), dim3(256), 0, s, g, I, Mq, grads, dI, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(frame_reduce_kernel, dim3((F + 63) / 64), dim3(64), 0, s, g, Mq, Jt, partial, F, dxi);
+  hipLaunchKernelGGL(frame_reduce_kernel, dim3(F), dim3(64), 0, s, g, Mq, Jt, partial, F, dxi);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_step(const double *dxi, int F, int t, const RefineAdam &a, double *state, double *xi_frames,
                               hipStream_t s) {
-  hipLaunchKernelGGL(refine_step_kernel, dim3(1), dim3(64), 0, s, dxi, F, t, a, state, xi_frames);
+  hipLaunchKernelGGL(refine_step_kernel, dim3(1), dim3(256), 0, s, dxi, F, t, a, state, xi_frames);
   return hipGetLastError();
 }
 
