@@ -411,6 +411,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the splat and batched lines")
     ap.add_argument("--profile-pass", action="store_true", help="one short pass for rocprofv3 (no oracle, no extras)")
+    ap.add_argument("--serial", action="store_true",
+                    help="time the step with the ingest launches on one stream (no overlap)")
     ap.add_argument("--extras-only", action="store_true",
                     help="for rocprofv3: only the splat, graph and batched measurements (one pass each)")
     ap.add_argument("--cache", default=None,
@@ -483,6 +485,10 @@ def main():
     vol.autotune(pid, frames[:1024], d["poses"][:1024], os.path.join(tempfile.gettempdir(), "usv_bench_tune.txt"))
     tile = vol.tiling(pid)
     frames_per_launch = vol.chunk(pid)
+    # consecutive ingest launches overlap on two library streams (joined before finalize);
+    # the profile pass and the roofline's launch timing run them one after another
+    overlap = not args.profile_pass and not args.serial
+    vol.set_ingest_overlap(overlap)
     nx, ny, nz = g.dims
     V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
     S = torch.empty_like(V)
@@ -512,6 +518,8 @@ def main():
             st = L.usv_ingest_frames(vol.h, pid, fptr, rp, fp, pptr, n, None)
             if st != 0:
                 raise RuntimeError("ingest failed: %d" % st)
+        if overlap:
+            L.usv_join(vol.h)
         host_submit.append(time.perf_counter() - th)
         if times is not None:
             ev[1].record()
@@ -553,10 +561,24 @@ def main():
                           "copy_bytes": snap.numel() * snap.element_size()}))
         return
 
-    # roofline of the ingest kernel: algorithmic bytes per launch / measured launch time
-    # kernel launches: each call of n frames is split into launches of frames_per_launch
+    # roofline of the ingest kernel: algorithmic bytes per launch / measured launch time,
+    # the launch time from steps with the launches one after another (as in the profiled
+    # pass); each call of n frames is split into launches of frames_per_launch
     n_kernel = sum(-(-n // frames_per_launch) for _, _, _, n in chunks)
-    per_launch_ms = phase[0] / n_kernel
+    overlapped_launch_ms = phase[0] / n_kernel
+    if overlap:
+        overlap = False
+        vol.set_ingest_overlap(False)
+        serial = 0.0
+        for _ in range(3):
+            tl = []
+            step(tl)
+            ev[3].synchronize()
+            serial += ev[0].elapsed_time(ev[1])
+        torch.cuda.synchronize()
+        per_launch_ms = serial / 3 / n_kernel
+    else:
+        per_launch_ms = overlapped_launch_ms
     per_chunk = q.get(timeout=600)
     proc.join(timeout=60)
     n_pix = 0
@@ -573,7 +595,9 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ingest_kernel (PNN scatter, %d frames per launch)" % frames_per_launch,
             "alg_bytes_per_launch": int(alg_bytes / n_kernel), "launch_ms": round(per_launch_ms, 5),
-            "distinct_voxels_per_launch": int(U / n_kernel)}
+            "distinct_voxels_per_launch": int(U / n_kernel),
+            "overlapped": {"ingest_phase_ms": round(phase[0], 4), "ms_per_launch": round(overlapped_launch_ms, 5),
+                           "achieved": round(alg_bytes / n_kernel / (overlapped_launch_ms * 1e-3) / 1e9, 1)}}
 
     extras = {}
     if not args.no_extras:
@@ -644,7 +668,8 @@ def main():
            "config": {"workload": "whole-spine sweep: 3600 frames 480x640 uint8 (0.1 mm px), 560 mm path with "
                                   "+-20 mm meander and +-5 deg jitter, grid 400x240x1120 @ 0.5 mm, calls of 64 "
                                   "frames, full finalize, ALG2 depth + slab projection h=2/5/10",
-                      "tile": list(tile), "frames_per_launch": frames_per_launch, "parallelism": "single GPU"},
+                      "tile": list(tile), "frames_per_launch": frames_per_launch,
+                      "ingest_streams": 1 if args.serial else 2, "parallelism": "single GPU"},
            "breakdown_ms": {"ingest": round(phase[0], 4), "finalize": round(phase[1], 4),
                             "segment_project": round(phase[2], 4)},
            "roofline": roof, "cpu_baseline": cpu}

@@ -164,6 +164,23 @@ const char *usv_last_error(const usv_volume *vol);
 usv_status usv_ingest_frames(usv_volume *vol, int32_t probe_id, const uint8_t *frames_dev, int64_t row_pitch,
                              int64_t frame_pitch, const double *poses_host, int32_t n, usv_box *dirty_out);
 
+/* Overlapped ingest (off by default).  Consecutive ingest launches of one volume are
+ * independent (integer atomics commute), but launches on one stream run back to back,
+ * each leaving the GPU partly idle at its start and end.  With overlap on, ingest
+ * launches alternate between two library streams (default priority).  A burst of
+ * ingest calls starts at the first ingest call after a join: the side streams then wait
+ * for everything enqueued on the volume's stream so far, and later calls of the burst
+ * add no waits (no host synchronisation calls per launch), so work the caller enqueues
+ * on the volume's stream during a burst is not seen by the burst's later launches.  The
+ * burst ends when the volume's stream waits for the side streams: at the next call of
+ * another kind on this volume (finalize, segment_project, sync, reset, export / import,
+ * autotune, graph calls, batched ingest) or at usv_join.  Until then the frames of the
+ * burst must stay unchanged and the accumulators must not be read; results are
+ * identical to the serial order.  Turning overlap off joins. */
+usv_status usv_set_ingest_overlap(usv_volume *vol, int32_t enable);
+/* make the volume's stream wait for any overlapped ingest launches (enqueue only) */
+usv_status usv_join(usv_volume *vol);
+
 /* Normalise + hole fill (Sec. II.C) into vol_u8_dev / state_dev ([nz][ny][nx] bytes;
  * state_dev may be NULL):
  *   V = cnt ? min(255, floor((2 sum + cnt) / (2 cnt))) : 0, state MEASURED / EMPTY;

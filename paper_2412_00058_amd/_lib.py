@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "USV_OK", -1: "USV_E_ARG", -2: "USV_E_OOM", -3: "USV_E_DEVICE
 EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
-    "usv_ingest_frames", "usv_ingest_frames_cut", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_vnn_create", "usv_vnn_reset", "usv_vnn_ingest",
+    "usv_ingest_frames", "usv_ingest_frames_cut", "usv_set_ingest_overlap", "usv_join", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_vnn_create", "usv_vnn_reset", "usv_vnn_ingest",
     "usv_vnn_finalize", "usv_vnn_destroy", "usv_extract_slices", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
     "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
@@ -94,6 +94,8 @@ def lib():
         "usv_destroy_volume": (I32, [P]),
         "usv_last_error": (C.c_char_p, [P]),
         "usv_ingest_frames": (I32, [P, I32, P, I64, I64, P, I32, C.POINTER(Box)]),
+        "usv_set_ingest_overlap": (I32, [P, I32]),
+        "usv_join": (I32, [P]),
         "usv_ingest_frames_cut": (I32, [P, I32, P, I64, I64, P, P, I32, C.POINTER(Box)]),
         "usv_cut_rows_alg1": (I32, [C.POINTER(ProbeDesc), P, I32, C.POINTER(CutParams), P]),
         "usv_extract_slices": (I32, [P, C.POINTER(C.c_int32 * 3), I32, I32, I32, P, P]),

@@ -77,6 +77,14 @@ struct usv_volume {
   size_t d_batch_bytes = 0;
   StagingRing batch_stage;
   uint32_t *d_counter = nullptr;
+  // overlapped ingest (usv_set_ingest_overlap): launches alternate between two library
+  // streams that wait for `stream` at each launch; `stream` waits for them lazily
+  bool overlap = false;
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
+  hipEvent_t main_ev = nullptr;
+  int next_side = 0;
+  bool side_pending = false;
 };
 
 struct usv_graph {
@@ -124,6 +132,39 @@ usv_status check_hip(usv_volume *v, hipError_t e, const char *what) {
     v->last_error = std::string(what) + ": " + hipGetErrorString(e);
   }
   return USV_E_DEVICE;
+}
+
+// The volume stream waits for every ingest launch issued on the side streams since the
+// burst began (one event per side stream, recorded here).
+usv_status join_side(usv_volume *v) {
+  if (!v->side_pending) return USV_OK;
+  for (int k = 0; k < 2; ++k) {
+    usv_status st = check_hip(v, hipEventRecord(v->side_ev[k], v->side[k]), "join ingest streams");
+    if (st == USV_OK) st = check_hip(v, hipStreamWaitEvent(v->stream, v->side_ev[k], 0), "join ingest streams");
+    if (st != USV_OK) return st;
+  }
+  v->side_pending = false;
+  return USV_OK;
+}
+
+// Stream of the next ingest launch: the volume stream, or (overlap) the next side stream.
+// The first launch of a burst (after a join) makes both side streams wait for everything
+// enqueued on the volume stream so far; later launches of the burst add no host calls.
+hipStream_t ingest_stream(usv_volume *v) {
+  if (!v->overlap) return v->stream;
+  if (!v->side_pending) {
+    if (hipEventRecord(v->main_ev, v->stream) != hipSuccess ||
+        hipStreamWaitEvent(v->side[0], v->main_ev, 0) != hipSuccess ||
+        hipStreamWaitEvent(v->side[1], v->main_ev, 0) != hipSuccess)
+      return nullptr;
+    v->side_pending = true;
+  }
+  return v->side[v->next_side];
+}
+
+// After a launch on ingest_stream(v): the next launch goes to the other side stream.
+void ingest_launched(usv_volume *v) {
+  if (v->overlap) v->next_side ^= 1;
 }
 
 bool finite_all(const double *p, int n) {
@@ -431,10 +472,12 @@ usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *fram
       for (int j = 0; j < 9; ++j) a.M[i][j] = maps[(size_t)(f0 + i) * 9 + j];
       if (rows) r.rows[i] = (*rows)[(size_t)(f0 + i)];
     }
-    const hipError_t e = rows ? launch_ingest_rows(r, cnt * per_frame, v->stream)
-                              : launch_ingest(a, cnt * per_frame, v->stream);
+    hipStream_t s = ingest_stream(v);
+    if (v->overlap && !s) return check_hip(v, hipErrorUnknown, "ingest stream fork");
+    const hipError_t e = rows ? launch_ingest_rows(r, cnt * per_frame, s) : launch_ingest(a, cnt * per_frame, s);
     usv_status st = check_hip(v, e, "ingest launch");
     if (st != USV_OK) return st;
+    ingest_launched(v);
   }
   return USV_OK;
 }
@@ -490,6 +533,10 @@ usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *s
 
 usv_status usv_reset(usv_volume *v) {
   if (!v) return USV_E_ARG;
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   const int64_t words = (int64_t)(usv_accumulator_bytes_of(v) / 4);
   usv_status st = check_hip(v, launch_zero_u32((uint32_t *)v->acc, words, v->stream), "zero accumulators");
   if (st != USV_OK) return st;
@@ -573,6 +620,10 @@ usv_status usv_add_probe(usv_volume *v, const usv_probe_desc *pd, int32_t *probe
 
 usv_status usv_sync(usv_volume *v) {
   if (!v) return USV_E_ARG;
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   if (v->count_dirty && v->sticky == USV_OK) {
     usv_status cs = count_check(v, false);
     if (cs != USV_OK) return cs;
@@ -592,12 +643,20 @@ usv_status usv_sync(usv_volume *v) {
 
 usv_status usv_export_accumulators(usv_volume *v, void *dst) {
   if (!v || !dst || (((uintptr_t)dst) & 3u)) return fail(v, USV_E_ARG, "bad destination");
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   return check_hip(v, launch_copy_u32((uint32_t *)dst, (const uint32_t *)v->acc,
                                       (int64_t)(usv_accumulator_bytes_of(v) / 4), v->stream), "export");
 }
 
 usv_status usv_import_accumulators(usv_volume *v, const void *src) {
   if (!v || !src || (((uintptr_t)src) & 3u)) return fail(v, USV_E_ARG, "bad source");
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   usv_status st = check_hip(v, launch_copy_u32((uint32_t *)v->acc, (const uint32_t *)src,
                                                (int64_t)(usv_accumulator_bytes_of(v) / 4), v->stream), "import");
   if (st != USV_OK) return st;
@@ -608,6 +667,14 @@ usv_status usv_import_accumulators(usv_volume *v, const void *src) {
 usv_status usv_destroy_volume(usv_volume *v) {
   if (!v) return USV_E_ARG;
   (void)hipStreamSynchronize(v->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (v->side[k]) {
+      (void)hipStreamSynchronize(v->side[k]);
+      (void)hipStreamDestroy(v->side[k]);
+    }
+    if (v->side_ev[k]) (void)hipEventDestroy(v->side_ev[k]);
+  }
+  if (v->main_ev) (void)hipEventDestroy(v->main_ev);
   for (ProbeState &p : v->probes) {
     if (p.d_spans) (void)hipFree(p.d_spans);
     if (p.d_mask) (void)hipFree(p.d_mask);
@@ -625,6 +692,31 @@ usv_status usv_destroy_volume(usv_volume *v) {
 }
 
 const char *usv_last_error(const usv_volume *v) { return v ? v->last_error.c_str() : "null volume"; }
+
+usv_status usv_set_ingest_overlap(usv_volume *v, int32_t enable) {
+  if (!v) return USV_E_ARG;
+  if (!enable) {
+    usv_status st = join_side(v);
+    v->overlap = false;
+    return st;
+  }
+  if (!v->side[0]) {
+    for (int k = 0; k < 2; ++k) {
+      if (hipStreamCreateWithFlags(&v->side[k], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&v->side_ev[k], hipEventDisableTiming) != hipSuccess)
+        return check_hip(v, hipErrorUnknown, "ingest streams");
+    }
+    if (hipEventCreateWithFlags(&v->main_ev, hipEventDisableTiming) != hipSuccess)
+      return check_hip(v, hipErrorUnknown, "ingest streams");
+  }
+  v->overlap = true;
+  return USV_OK;
+}
+
+usv_status usv_join(usv_volume *v) {
+  if (!v) return USV_E_ARG;
+  return join_side(v);
+}
 
 usv_status usv_ingest_frames(usv_volume *v, int32_t probe_id, const uint8_t *frames, int64_t row_pitch,
                              int64_t frame_pitch, const double *poses, int32_t n, usv_box *dirty_out) {
@@ -678,6 +770,10 @@ usv_status usv_ingest_frames_cut(usv_volume *v, int32_t probe_id, const uint8_t 
 
 usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, uint8_t *state) {
   if (!v || !vol_u8) return fail(v, USV_E_ARG, "null output");
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   FinalizeArgs a{};
   a.sum = v->sum;
@@ -708,6 +804,10 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
 usv_status usv_segment_project(usv_volume *v, const usv_seg_params *pr, const uint8_t *vol_u8, const uint8_t *state,
                                int16_t *depth, float *mean, float *max) {
   if (!v || !pr || !vol_u8 || !state || !depth || !mean || !max) return fail(v, USV_E_ARG, "null argument");
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   if (pr->mode < 0 || pr->mode > 2 || pr->n_half < 1 || pr->n_half > 4) return fail(v, USV_E_ARG, "bad mode / n_half");
   for (int i = 0; i < pr->n_half; ++i)
     if (pr->half[i] < 0 || pr->half[i] > 255) return fail(v, USV_E_ARG, "half width out of range");
@@ -873,6 +973,14 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
       n_sweeps > 4096 || !vols[0])
     return USV_E_ARG;
   usv_volume *owner = vols[0];
+  for (int32_t i = 0; i < n_sweeps; ++i) {
+    usv_volume *v = vols[i];
+    if (!v || !v->side_pending) continue;
+    if (join_side(v) != USV_OK) return USV_E_DEVICE;   // records the side events
+    if (v != owner)
+      for (int k = 0; k < 2; ++k)
+        if (hipStreamWaitEvent(owner->stream, v->side_ev[k], 0) != hipSuccess) return USV_E_DEVICE;
+  }
   // entry 2i: ordinary frames of sweep i; 2i+1: frames that need the small-tile tiling
   std::vector<std::vector<float>> maps((size_t)n_sweeps * 2);
   std::vector<std::vector<int32_t>> fidx((size_t)n_sweeps * 2);
@@ -976,6 +1084,10 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
                         const double *poses, int32_t n, const char *cache_path) {
   if (!v || probe_id < 0 || probe_id >= (int32_t)v->probes.size() || n < 1 || !frames || !poses)
     return fail(v, USV_E_ARG, "bad autotune arguments");
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   ProbeState &p = v->probes[(size_t)probe_id];
   if (row_pitch < p.W || (n > 1 && frame_pitch < (int64_t)(p.H - 1) * row_pitch + p.W))
     return fail(v, USV_E_ARG, "pitch smaller than the image");
@@ -1096,6 +1208,10 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
 
 usv_status usv_graph_create(usv_volume *v, int32_t probe_id, usv_graph **out) {
   if (!v || !out || probe_id < 0 || probe_id >= (int32_t)v->probes.size()) return fail(v, USV_E_ARG, "bad graph args");
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   *out = nullptr;
   const ProbeState &p = v->probes[(size_t)probe_id];
   usv_graph *g = new (std::nothrow) usv_graph();
@@ -1146,6 +1262,10 @@ usv_status usv_graph_create(usv_volume *v, int32_t probe_id, usv_graph **out) {
 usv_status usv_graph_launch(usv_graph *g, const uint8_t *frame_host, const double *pose_host, usv_box *dirty_out) {
   if (!g || !frame_host || !pose_host) return USV_E_ARG;
   usv_volume *v = g->vol;
+  {
+    usv_status js = join_side(v);
+    if (js != USV_OK) return js;
+  }
   if (dirty_out) *dirty_out = empty_box();
   const ProbeState &p = v->probes[(size_t)g->probe_id];
   float M[9];

@@ -207,6 +207,14 @@ class Volume:
                                       P.ctypes.data_as(C.c_void_p), n, C.byref(box)), self.h)
         return box
 
+    def set_ingest_overlap(self, enable: bool = True):
+        """Overlap consecutive ingest launches on two library streams (frames of pending
+        calls must stay unchanged until the next non-ingest call or join())."""
+        check(lib().usv_set_ingest_overlap(self.h, 1 if enable else 0), self.h)
+
+    def join(self):
+        check(lib().usv_join(self.h), self.h)
+
     def ingest_cut(self, probe_id, frames: torch.Tensor, poses, rows) -> Box:
         """ingest() restricted to each frame's band of rows (int32 [F, 2] first/last row,
         host array or tensor): the cut images Img_C of the tissue segmentation."""

@@ -96,8 +96,9 @@ def test_graph_with_convex_mask_equals_oracle():
 
 def test_whole_spine_sweep_full_size_bit_exact():
     """3600 frames of 480 x 640 into the 400 x 240 x 1120 grid, ingested in calls of 64 with
-    the autotuned tiling (the benchmark's configuration); accumulators, normalised volume,
-    state, depth map and slab projections equal the oracle's bit for bit."""
+    the autotuned tiling and overlapped launches (the benchmark's configuration);
+    accumulators, normalised volume, state, depth map and slab projections equal the
+    oracle's bit for bit."""
     from paper_2412_00058_amd import seg_params, SEG_ALG2
     say("case: whole-spine sweep, full size")
     d = synth.cfg2()
@@ -107,6 +108,7 @@ def test_whole_spine_sweep_full_size_bit_exact():
     fr = to_dev(d["frames"])
     vol.autotune(pid, fr[:512], d["poses"][:512], None)
     say("  tile", vol.tiling(pid))
+    vol.set_ingest_overlap(True)
     F = fr.shape[0]
     for k in range(0, F, 64):
         vol.ingest(pid, fr[k:k + 64], d["poses"][k:k + 64])
@@ -176,3 +178,56 @@ def test_realtime_pipeline_equals_full_path():
     frames, renders = pl.stats()
     assert frames == 64 and renders >= 64 // 7
     pl.close()
+
+
+def test_overlapped_ingest_equals_serial_and_oracle():
+    """Ingest launches alternating on two library streams: the result equals the oracle
+    after finalize / export / sync (which join), across a reset, after turning overlap
+    off, with the cut ingest, and when an overlapped volume enters a batched call."""
+    from paper_2412_00058_amd import ingest_batched
+    say("case: overlapped ingest")
+    d = synth.cfg1()
+    g = d["grid"]
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    vol.set_tiling(pid, 32, 32)
+    vol.set_ingest_overlap(True)
+    fr = to_dev(d["frames"])
+    for k in range(0, 64, 8):
+        vol.ingest(pid, fr[k:k + 8], d["poses"][k:k + 8])
+    V, S = vol.finalize()
+    vol.sync()
+    acc = oracle.Accum(g)
+    acc.ingest(d["frames"], d["poses"], d["probe"])
+    assert_accum_equal(vol, acc, "overlapped")
+    Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    # reset joins first; then a few calls and an export (which joins)
+    vol.reset()
+    for k in range(0, 20, 4):
+        vol.ingest(pid, fr[k:k + 4], d["poses"][k:k + 4])
+    snap = vol.export_accumulators()
+    vol.sync()
+    acc20 = oracle.Accum(g)
+    acc20.ingest(d["frames"][:20], d["poses"][:20], d["probe"])
+    s_, c_ = vol.host_accumulators()
+    assert np.array_equal(s_, acc20.sum) and np.array_equal(c_, acc20.cnt)
+    assert torch.equal(snap, vol.acc)
+    # cut ingest overlapped, then overlap off
+    rows = np.array([[10 + k % 30, 40 + k % 50] for k in range(64)], dtype=np.int32)
+    vol.reset()
+    vol.ingest_cut(pid, fr[:32], d["poses"][:32], rows[:32])
+    vol.ingest_cut(pid, fr[32:], d["poses"][32:], rows[32:])
+    vol.set_ingest_overlap(False)
+    vol.sync()
+    accc = oracle.Accum(g)
+    accc.ingest(d["frames"], d["poses"], d["probe"], rows=rows)
+    assert_accum_equal(vol, accc, "overlapped cut")
+    # a pending overlapped volume in a batched call
+    vol.set_ingest_overlap(True)
+    vol.reset()
+    vol.ingest(pid, fr[:32], d["poses"][:32])
+    ingest_batched([(vol, pid, fr[32:], d["poses"][32:])])
+    vol.sync()
+    assert_accum_equal(vol, acc, "overlapped then batched")
+    vol.close()
