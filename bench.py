@@ -139,9 +139,14 @@ def counters_summary(fetch_db, write_db, out_json, atomic_db=None):
 
 
 def ingest_source_hash():
+    """SHA-256 of what defines the ingest kernel: ingest.hip and the ingest section of
+    usv_internal.h (from its start to the finalize section)."""
+    csrc = os.path.join(ROOT, "paper_2412_00058_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("ingest.hip", "usv_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2412_00058_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(csrc, "ingest.hip"), "rb").read())
+    hdr = open(os.path.join(csrc, "usv_internal.h"), "rb").read()
+    cut = hdr.find(b"// ---- finalize")
+    h.update(hdr if cut < 0 else hdr[:cut])
     return h.hexdigest()
 
 
