@@ -77,20 +77,20 @@ def time_oracle_step(d, seg):
     return time.perf_counter() - t0
 
 
-def traffic_from_profile(src_hash):
+def traffic_from_profile(src_hash, tile):
     """HBM traffic per ingest launch from the committed rocprofv3 counter summary, if it was
-    taken on the current ingest kernel source; otherwise None."""
+    taken on the current ingest kernel source with the same tile shape; otherwise None."""
     p = os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json")
     try:
         rec = json.load(open(p))
     except (OSError, ValueError):
         return None
-    if rec.get("ingest_source_sha256") != src_hash:
+    if rec.get("ingest_source_sha256") != src_hash or rec.get("tile") != list(tile):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def counters_summary(fetch_db, write_db, out_json, atomic_db=None):
+def counters_summary(fetch_db, write_db, out_json, atomic_db=None, tile=None):
     """Summarise two rocprofv3 --pmc runs of `bench.py --profile-pass` (FETCH_SIZE, then
     WRITE_SIZE; rocpd sqlite output) into HBM bytes per ingest launch.  Each counter is
     scaled by what it reads for copy_u32_kernel, which the profile pass runs once on a
@@ -119,7 +119,7 @@ def counters_summary(fetch_db, write_db, out_json, atomic_db=None):
     kf, kw = copy_bytes / f_copy, copy_bytes / w_copy
     f_ing, n_f = fetch["ingest_kernel"]
     w_ing, n_w = write["ingest_kernel"]
-    rec = {"ingest_source_sha256": ingest_source_hash(),
+    rec = {"ingest_source_sha256": ingest_source_hash(), "tile": list(tile) if tile else None,
            "fetch_kib_per_dispatch": round(f_ing, 1), "write_kib_per_dispatch": round(w_ing, 1),
            "dispatches": [n_f, n_w], "copy_bytes": copy_bytes,
            "copy_fetch_kib": round(f_copy / 1024.0, 1), "copy_write_kib": round(w_copy / 1024.0, 1),
@@ -426,11 +426,13 @@ def main():
     ap.add_argument("--counters-summary", nargs="+", metavar="DB", default=None,
                     help="no GPU: summarise the rocprofv3 --pmc result databases of the profile pass "
                          "(FETCH_SIZE, WRITE_SIZE[, TCC_EA0_ATOMIC_sum]) into profiles/ingest_cfg2_counters.json")
+    ap.add_argument("--counters-tile", nargs=2, type=int, metavar=("W", "H"), default=None,
+                    help="the ingest tile shape of the profiled pass (printed by it), stored with the summary")
     args = ap.parse_args()
     if args.counters_summary:
         dbs = args.counters_summary
         counters_summary(dbs[0], dbs[1], os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json"),
-                         dbs[2] if len(dbs) > 2 else None)
+                         dbs[2] if len(dbs) > 2 else None, args.counters_tile)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build is single-GPU only (see DESIGN.md, sharding plan)",
@@ -487,11 +489,13 @@ def main():
     # tile shape picked by the library's autotuner on the first 1024 frames (untimed); the
     # choice is cached in a temp file so that profiled passes reuse it without re-tuning
     import tempfile
+    # consecutive ingest launches overlap on two library streams (joined before finalize);
+    # the tile is tuned in that mode; the profile pass and the roofline's launch timing
+    # then run the launches one after another with the same tile
+    vol.set_ingest_overlap(not args.serial)
     vol.autotune(pid, frames[:1024], d["poses"][:1024], os.path.join(tempfile.gettempdir(), "usv_bench_tune.txt"))
     tile = vol.tiling(pid)
     frames_per_launch = vol.chunk(pid)
-    # consecutive ingest launches overlap on two library streams (joined before finalize);
-    # the profile pass and the roofline's launch timing run them one after another
     overlap = not args.profile_pass and not args.serial
     vol.set_ingest_overlap(overlap)
     nx, ny, nz = g.dims
@@ -562,7 +566,7 @@ def main():
         # one plain copy of known size (the accumulator export) to calibrate byte counters
         snap = vol.export_accumulators()
         torch.cuda.synchronize()
-        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step,
+        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step, "tile": list(tile),
                           "copy_bytes": snap.numel() * snap.element_size()}))
         return
 
@@ -595,7 +599,7 @@ def main():
     # distinct voxels are counted per 64-frame call; with smaller launches this undercounts
     # the accumulator bytes (a conservative roofline)
     achieved = alg_bytes / n_kernel / (per_launch_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(ingest_source_hash())
+    traffic = traffic_from_profile(ingest_source_hash(), tile)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ingest_kernel (PNN scatter, %d frames per launch)" % frames_per_launch,

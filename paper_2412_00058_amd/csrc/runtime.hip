@@ -1094,8 +1094,8 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, v->device) != hipSuccess) return check_hip(v, hipErrorUnknown, "device query");
   char key[256];
-  std::snprintf(key, sizeof(key), "%s|%dx%d|%.6g|%.6g|%.4f", prop.gcnArchName, p.W, p.H, p.sx / v->s, p.sy / v->s,
-                p.mask_density);
+  std::snprintf(key, sizeof(key), "%s|%dx%d|%.6g|%.6g|%.4f|%s", prop.gcnArchName, p.W, p.H, p.sx / v->s,
+                p.sy / v->s, p.mask_density, v->overlap ? "overlap" : "serial");
   for (char *c = key; *c; ++c)
     if (*c == ' ') *c = '_';
   if (cache_path) {
@@ -1138,6 +1138,14 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   tmp.sum = (uint32_t *)scratch;
   tmp.cnt32 = (uint32_t *)((uint8_t *)scratch + 4 * v->nvox);
   tmp.d_err = err;
+  // trials launch the way the volume will: with overlap on, on the volume's side streams
+  // (shared handles, joined after each trial run)
+  tmp.overlap = v->overlap;
+  for (int k = 0; k < 2; ++k) {
+    tmp.side[k] = v->side[k];
+    tmp.side_ev[k] = v->side_ev[k];
+  }
+  tmp.main_ev = v->main_ev;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -1157,7 +1165,8 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
     auto run = [&]() {
       usv_status r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);
       if (r == USV_OK && !sfidx.empty()) r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
-      return r;
+      const usv_status j = join_side(&tmp);
+      return r != USV_OK ? r : j;
     };
     (void)launch_zero_u32((uint32_t *)scratch, (int64_t)(bytes / 4), v->stream);
     if (run() != USV_OK) return -1.0f;   // warm-up

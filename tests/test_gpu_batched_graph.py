@@ -91,6 +91,26 @@ def test_autotune_keeps_results_and_caches():
     assert_accum_equal(vol, oracle_accum(d), "autotuned")
 
 
+def test_autotune_in_overlap_mode():
+    """Trials run with overlapped launches when the volume has overlap on; the cache keeps
+    the serial and the overlapped choice apart; results stay exact."""
+    say("case: autotune overlapped")
+    d = synth.cfg1()
+    fr = to_dev(d["frames"])
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.txt")
+        vol = gpu_volume(d["grid"])
+        pid = add_probe(vol, d["probe"])
+        vol.autotune(pid, fr[:32], d["poses"][:32], cache)
+        vol.set_ingest_overlap(True)
+        vol.autotune(pid, fr[:32], d["poses"][:32], cache)
+        lines = [l for l in open(cache).read().splitlines() if l.strip()]
+        assert len(lines) == 2 and sum("overlap" in l.split()[0] for l in lines) == 1
+        vol.ingest(pid, fr, d["poses"])
+        vol.sync()
+        assert_accum_equal(vol, oracle_accum(d), "autotuned overlapped")
+
+
 def test_graph_single_frame_ingest_equals_chunked():
     from paper_2412_00058_amd import Graph
     say("case: graph per-frame")

@@ -106,9 +106,9 @@ def test_whole_spine_sweep_full_size_bit_exact():
     vol = gpu_volume(g)
     pid = add_probe(vol, d["probe"])
     fr = to_dev(d["frames"])
+    vol.set_ingest_overlap(True)
     vol.autotune(pid, fr[:512], d["poses"][:512], None)
     say("  tile", vol.tiling(pid))
-    vol.set_ingest_overlap(True)
     F = fr.shape[0]
     for k in range(0, F, 64):
         vol.ingest(pid, fr[k:k + 64], d["poses"][k:k + 64])
