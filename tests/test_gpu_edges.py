@@ -231,3 +231,64 @@ def test_overlapped_ingest_equals_serial_and_oracle():
     vol.sync()
     assert_accum_equal(vol, acc, "overlapped then batched")
     vol.close()
+
+
+def test_new_entry_points_edge_cases():
+    """Degenerate inputs of the image-space cut, VNN, DW, slices and refinement: empty
+    calls, bands that keep nothing or lie outside the image, frames off the grid, a
+    non-finite pose that keeps its frame number, a refinement with no moving frame."""
+    from paper_2412_00058_amd import VNN, SplatContext, UsvError, cut_params, cut_rows_alg2, extract_slices
+    say("case: edge cases of the newer entry points")
+    d = synth.cfg1()
+    g, p = d["grid"], d["probe"]
+    fr = to_dev(d["frames"])
+    # cut ingest: every band empty or outside the image -> nothing, empty box
+    vol = gpu_volume(g)
+    pid = add_probe(vol, p)
+    rows = np.array([[5, 4], [p.height, p.height + 9], [-20, -1], [3, 2]], dtype=np.int32)
+    box = vol.ingest_cut(pid, fr[:4], d["poses"][:4], rows)
+    vol.sync()
+    assert _empty(box)
+    s, c = vol.host_accumulators()
+    assert not s.any() and not c.any()
+    box = vol.ingest_cut(pid, fr[:0], d["poses"][:0], rows[:0])
+    assert _empty(box)
+    # Alg. 2 on zero frames is a no-op; on frames with no contour every band is the fallback
+    assert cut_rows_alg2(fr[:0], cut_params()).shape == (0, 2)
+    flat = torch.full((3, p.height, p.width), 60, dtype=torch.uint8, device="cuda")
+    r = cut_rows_alg2(flat, cut_params(fallback_row=20, half_rows=4)).cpu().numpy()
+    assert (r == [16, 24]).all()
+    # VNN: empty call, frames off the grid, a non-finite pose that still takes a number
+    vn = VNN(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, 0.5)
+    vn.ingest(fr[:0], d["poses"][:0])
+    off = d["poses"][:3].copy()
+    off[:, 0, 3] += 1000.0
+    vn.ingest(fr[:3], off)
+    torch.cuda.synchronize()
+    assert (vn.keys == -1).all()
+    bad = d["poses"][:6].copy()
+    bad[0, 0, 0] = np.nan
+    vn.reset()
+    vn.ingest(fr[:6], bad)
+    ref = oracle.vnn_keys(g, d["frames"][:6], bad, p, 0.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(vn.keys.cpu().numpy().view(np.uint64).reshape(ref.shape), ref)
+    vn.close()
+    # DW: zero frames and frames off the grid add nothing
+    ctx = SplatContext(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, 8)
+    acc = ctx.dw_clear()
+    ctx.dw_ingest(acc, fr[:0], to_dev(d["poses"][:0]))
+    ctx.dw_ingest(acc, fr[:3], to_dev(off))
+    torch.cuda.synchronize()
+    assert not acc.any()
+    with pytest.raises(UsvError):
+        ctx.dw_ingest(acc, fr[:9], to_dev(d["poses"][:9]))     # more than max_frames
+    # refinement with a single (even) frame: no moving frame, no overlap term, loss 0
+    I = torch.rand((1, p.height, p.width), device="cuda")
+    xi, L = ctx.refine_motion(I, to_dev(d["poses"][:1]), iters=3)
+    torch.cuda.synchronize()
+    assert not xi.any() and float(L.abs().max()) == 0.0
+    # slices: a range past the end is rejected
+    V, _ = gpu_volume(g).finalize()
+    with pytest.raises(UsvError):
+        extract_slices(V, 2, g.dims[2] - 1, 2)
