@@ -146,6 +146,7 @@ usv_status usv_cut_rows_alg2(const uint8_t *frames, int64_t row_pitch, int64_t f
   if (!p || F < 0 || W < 1 || H < 1 || W > 32767 || H > 32767) return USV_E_ARG;
   if (F > 0 && (!frames || !scratch || !rows)) return USV_E_ARG;
   if (row_pitch < W || (F > 1 && frame_pitch < (int64_t)(H - 1) * row_pitch + W) || frame_pitch < 0) return USV_E_ARG;
+  if ((int64_t)H * row_pitch >= ((int64_t)1 << 32)) return USV_E_UNSUPPORTED;   // 32-bit row offsets in a frame
   if (p->k < 1 || p->k > 64 || p->y_lo < 0 || p->r < 0 || p->r > 64 || p->fallback_row < 0 || p->fallback_row >= H ||
       p->half_rows < 0 || p->half_rows > 32767)
     return USV_E_ARG;

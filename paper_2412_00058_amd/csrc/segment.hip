@@ -31,8 +31,10 @@ __device__ __forceinline__ bool xcd_block(int gx, int nbands, int &bx, int &band
 __host__ __forceinline__ unsigned xcd_blocks(int gx, int nbands) { return (unsigned)(8 * ((nbands + 7) / 8) * gx); }
 
 // kC columns per lane (4: one 32-bit load covers a lane's four columns of a row, which
-// needs nx % 4 == 0 and a 4-byte aligned volume; else 1).
-template <int kC>
+// needs nx % 4 == 0 and a 4-byte aligned volume; else 1).  K: the window length k when it
+// is 1 .. kUnroll (the row leaving the window is then in a batch already loaded), 0 for
+// any k (that row is loaded again).
+template <int kC, int K>
 __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
   __shared__ int32_t best_s_sh[kSeg][64][kC], best_y_sh[kSeg][64][kC];
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
@@ -46,16 +48,21 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
     best[c] = -1;
     best_s[c] = 0;
   }
+  // row offsets are 32-bit (a plane holds < 2^32 bytes) and wave-uniform: each load is
+  // one 64-bit add of a scalar offset to the lane's column pointer
+  const uint32_t rp = (uint32_t)a.row_pitch;
   auto row = [&](const uint8_t *col, int y) -> uint32_t {
-    if (kC == 4) return *reinterpret_cast<const uint32_t *>(col + (int64_t)y * a.row_pitch);
-    return col[(int64_t)y * a.row_pitch];
+    const uint32_t off = (uint32_t)y * rp;
+    if (kC == 4) return *reinterpret_cast<const uint32_t *>(col + off);
+    return col[off];
   };
   if (x < a.nx && ymax >= a.y_lo) {
     const uint8_t *col = a.V + (int64_t)z * a.plane_pitch + x;
     const int len = ymax - a.y_lo + 1;
     const int per = (len + kSeg - 1) / kSeg;
-    const int yhi = ymax - seg * per;                  // this segment: y in [ylo, yhi]
-    const int ylo = max(a.y_lo, yhi - per + 1);
+    // this segment: y in [ylo, yhi]; the same for every lane of the wave
+    const int yhi = __builtin_amdgcn_readfirstlane(ymax - seg * per);
+    const int ylo = __builtin_amdgcn_readfirstlane(max(a.y_lo, yhi - per + 1));
     if (yhi >= ylo) {
       int below[kC];   // sum of V(y+1 .. y+k) for y = yhi, per column
 #pragma unroll
@@ -66,28 +73,74 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
         for (int c = 0; c < kC; ++c) below[c] += (int)((w >> (8 * c)) & 0xFFu);
       }
       const int thr = a.k * a.tau_G;
-      for (int yb = yhi; yb >= ylo; yb -= kUnroll) {
-        uint32_t here[kUnroll], leave[kUnroll];
+      auto score_row = [&](int y, uint32_t hv, uint32_t lv) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int y = yb - u;
-          here[u] = y >= ylo ? row(col, y) : 0u;
-          leave[u] = y >= ylo ? row(col, y + a.k) : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int y = yb - u;
-          if (y < ylo) break;
-#pragma unroll
-          for (int c = 0; c < kC; ++c) {
-            const int h = (int)((here[u] >> (8 * c)) & 0xFFu), l = (int)((leave[u] >> (8 * c)) & 0xFFu);
-            const int sc = a.k * h - below[c];
-            if (h >= a.tau_I && sc >= thr && (best[c] < 0 || sc > best_s[c])) {
-              best[c] = y;
-              best_s[c] = sc;
-            }
-            below[c] += h - l;
+        for (int c = 0; c < kC; ++c) {
+          const int h = (int)((hv >> (8 * c)) & 0xFFu), l = (int)((lv >> (8 * c)) & 0xFFu);
+          const int sc = (int)__umul24((uint32_t)a.k, (uint32_t)h) - below[c];   // k <= 64, h <= 255
+          if (h >= a.tau_I && sc >= thr && (best[c] < 0 || sc > best_s[c])) {
+            best[c] = y;
+            best_s[c] = sc;
           }
+          below[c] += h - l;
+        }
+      };
+      if (K > 0) {
+        // batches of kUnroll rows, triple buffered (previous, current, next): the next
+        // batch's loads are issued before the current one is scored, and the row leaving
+        // the window, y + K, sits in the current or the previous batch.  Rows outside
+        // [ylo, ny - 1] re-read a row inside it and are not used.
+        const int ytop = a.ny - 1;
+        auto load_batch = [&](int yb, uint32_t *H) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) H[u] = row(col, min(max(yb - u, ylo), ytop));
+        };
+        auto score_batch = [&](int yb, const uint32_t *H, const uint32_t *P) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            if (yb - u < ylo) break;
+            score_row(yb - u, H[u], u >= K ? H[u - K] : P[u - K + kUnroll]);
+          }
+        };
+        uint32_t B0[kUnroll], B1[kUnroll], B2[kUnroll];
+        load_batch(yhi + kUnroll, B0);   // rows yhi + 1 .. yhi + kUnroll
+        load_batch(yhi, B1);
+        for (int yb = yhi; yb >= ylo; yb -= 3 * kUnroll) {
+          if (yb - kUnroll >= ylo) load_batch(yb - kUnroll, B2);
+          score_batch(yb, B1, B0);
+          if (yb - kUnroll < ylo) break;
+          if (yb - 2 * kUnroll >= ylo) load_batch(yb - 2 * kUnroll, B0);
+          score_batch(yb - kUnroll, B2, B1);
+          if (yb - 2 * kUnroll < ylo) break;
+          if (yb - 3 * kUnroll >= ylo) load_batch(yb - 3 * kUnroll, B1);
+          score_batch(yb - 2 * kUnroll, B0, B2);
+        }
+      } else {
+        // any k: batches of kUnroll rows, double buffered, each row's leaving row loaded
+        // beside it; rows past the segment's end re-read row ylo and are not used
+        auto load_batch = [&](int yb, uint32_t *H, uint32_t *Lv) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int y = max(yb - u, ylo);
+            H[u] = row(col, y);
+            Lv[u] = row(col, y + a.k);
+          }
+        };
+        auto score_batch = [&](int yb, const uint32_t *H, const uint32_t *Lv) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            if (yb - u < ylo) break;
+            score_row(yb - u, H[u], Lv[u]);
+          }
+        };
+        uint32_t Ha[kUnroll], La[kUnroll], Hb[kUnroll], Lb[kUnroll];
+        load_batch(yhi, Ha, La);
+        for (int yb = yhi; yb >= ylo; yb -= 2 * kUnroll) {
+          if (yb - kUnroll >= ylo) load_batch(yb - kUnroll, Hb, Lb);
+          score_batch(yb, Ha, La);
+          if (yb - kUnroll < ylo) break;
+          if (yb - 2 * kUnroll >= ylo) load_batch(yb - 2 * kUnroll, Ha, La);
+          score_batch(yb - kUnroll, Hb, Lb);
         }
       }
     }
@@ -230,11 +283,27 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
 
 }  // namespace
 
+template <int kC>
+void launch_contour_k(const SegArgs &a, dim3 grid, hipStream_t s) {
+  switch (a.k) {
+    case 1: hipLaunchKernelGGL((raw_depth_kernel<kC, 1>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((raw_depth_kernel<kC, 2>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((raw_depth_kernel<kC, 3>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((raw_depth_kernel<kC, 4>), grid, dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((raw_depth_kernel<kC, 5>), grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((raw_depth_kernel<kC, 6>), grid, dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((raw_depth_kernel<kC, 7>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((raw_depth_kernel<kC, 8>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((raw_depth_kernel<kC, 0>), grid, dim3(256), 0, s, a); break;
+  }
+}
+
 hipError_t launch_contour(const SegArgs &a, hipStream_t s) {
+  static_assert(kUnroll == 8, "the k dispatch covers 1 .. kUnroll");
   if (a.nx % 4 == 0 && a.row_pitch % 4 == 0 && a.plane_pitch % 4 == 0 && (((uintptr_t)a.V) & 3u) == 0)
-    hipLaunchKernelGGL(raw_depth_kernel<4>, dim3(xcd_blocks((a.nx + 255) / 256, a.nz)), dim3(256), 0, s, a);
+    launch_contour_k<4>(a, dim3(xcd_blocks((a.nx + 255) / 256, a.nz)), s);
   else
-    hipLaunchKernelGGL(raw_depth_kernel<1>, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), dim3(256), 0, s, a);
+    launch_contour_k<1>(a, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), s);
   return hipGetLastError();
 }
 

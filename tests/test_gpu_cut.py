@@ -152,3 +152,25 @@ def test_spine_volume_whole_sweep_full_size():
                 rows=oracle.cut_rows_alg1(d["poses"], d["probe"], axis=2, K=22.0 / 280.0, D_mm=28.0, L_mm=560.0,
                                           z1_mm=z1, half_rows=60))
     assert_accum_equal(vol, acc1, "spine volume alg1")
+
+
+@pytest.mark.parametrize("k", [1, 8, 12])
+def test_contour_window_lengths(k):
+    """Window lengths at both ends of the scan's specialised range (1, 8) and past it (12,
+    the general path), on a frame stack (Alg. 2 bands) and on a volume (ALG2 depth)."""
+    from paper_2412_00058_amd import seg_params, SEG_ALG2
+    say("case: contour window", k)
+    d = synth.cfg1()
+    kw = dict(y_lo=2, k=k, tau_I=128, tau_G=30, r=2, fallback_row=45, half_rows=3)
+    got = alg2_gpu(to_dev(d["frames"]), **kw)
+    assert np.array_equal(got, oracle.cut_rows_alg2(d["frames"], **kw))
+    vol = gpu_volume(d["grid"])
+    pid = add_probe(vol, d["probe"])
+    vol.ingest(pid, to_dev(d["frames"]), d["poses"])
+    V, S = vol.finalize()
+    sk = dict(y_lo=1, k=k, tau_I=128, tau_G=30, r=2, fallback_y=20, half=(2, 5))
+    dep, mean, mx = vol.segment_project(seg_params(mode=SEG_ALG2, **sk), V, S)
+    vol.sync()
+    do, mo, xo = oracle.segment(d["grid"], V.cpu().numpy(), S.cpu().numpy(), oracle.seg_params(mode=oracle.ALG2, **sk))
+    assert np.array_equal(dep.cpu().numpy(), do)
+    assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32))
