@@ -57,23 +57,32 @@ __global__ __launch_bounds__(256) void image_median_kernel(const int16_t *__rest
 }
 
 // One thread per frame: lower median of the valid per-image depths over [f - r, f + r]
-// (clipped to the sweep), by rank counting (window of at most 129 frames).
-__global__ void cut_band_kernel(const int16_t *__restrict__ cn, int F, int r, int fallback, int h, int H,
-                                int32_t *__restrict__ rows) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// (clipped to the sweep), by rank counting (window of at most 129 frames) over the
+// block's frames and their r-halo staged in LDS.
+constexpr int kBandBlock = 256, kMaxR = 64;
+__global__ __launch_bounds__(kBandBlock) void cut_band_kernel(const int16_t *__restrict__ cn, int F, int r,
+                                                              int fallback, int h, int H, int32_t *__restrict__ rows) {
+  __shared__ int16_t sc[kBandBlock + 2 * kMaxR];
+  const int f0 = blockIdx.x * kBandBlock;
+  for (int e = threadIdx.x; e < kBandBlock + 2 * r; e += kBandBlock) {
+    const int g = f0 - r + e;
+    sc[e] = (g >= 0 && g < F) ? cn[g] : (int16_t)-1;   // outside the sweep: not valid
+  }
+  __syncthreads();
+  const int f = f0 + threadIdx.x;
   if (f >= F) return;
-  const int a = max(0, f - r), b = min(F - 1, f + r);
+  const int16_t *w = sc + threadIdx.x;   // w[0 .. 2r] = frames f - r .. f + r
   int m = 0;
-  for (int j = a; j <= b; ++j) m += cn[j] >= 0 ? 1 : 0;
+  for (int j = 0; j <= 2 * r; ++j) m += w[j] >= 0 ? 1 : 0;
   int d = fallback;
   if (m > 0) {
     const int k = (m - 1) / 2;
-    for (int j = a; j <= b; ++j) {
-      const int vj = cn[j];
+    for (int j = 0; j <= 2 * r; ++j) {
+      const int vj = w[j];
       if (vj < 0) continue;
       int less = 0, leq = 0;
-      for (int i = a; i <= b; ++i) {
-        const int vi = cn[i];
+      for (int i = 0; i <= 2 * r; ++i) {
+        const int vi = w[i];
         if (vi < 0) continue;
         less += vi < vj ? 1 : 0;
         leq += vi <= vj ? 1 : 0;
@@ -96,7 +105,8 @@ hipError_t launch_image_cut(const int16_t *raw, int F, int W, int H, int r, int 
   hipLaunchKernelGGL(image_median_kernel, dim3(F), dim3(256), 0, s, raw, W, H, cn);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cut_band_kernel, dim3((F + 255) / 256), dim3(256), 0, s, cn, F, r, fallback, h, H, rows);
+  hipLaunchKernelGGL(cut_band_kernel, dim3((F + kBandBlock - 1) / kBandBlock), dim3(kBandBlock), 0, s, cn, F, r,
+                     fallback, h, H, rows);
   return hipGetLastError();
 }
 
