@@ -489,15 +489,6 @@ __global__ __launch_bounds__(256) void count_final_kernel(const unsigned long lo
   if (threadIdx.x == 0 && stored != added) err[0] = 1u;
 }
 
-__global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
-}
-
-__global__ void copy_u32_kernel(uint32_t *dst, const uint32_t *src, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
 
 }  // namespace
 
@@ -537,28 +528,12 @@ hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
-
 hipError_t launch_count_check(const uint32_t *cnt32, int64_t n_words, unsigned long long *kept,
                               unsigned long long *partials, uint32_t *err, bool store, hipStream_t s) {
   hipLaunchKernelGGL(count_sum_kernel, dim3(kCheckBlocks), dim3(256), 0, s, cnt32, n_words, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(count_final_kernel, dim3(1), dim3(256), 0, s, partials, kCheckBlocks, kept, err, store ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(copy_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
 
