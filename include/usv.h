@@ -24,7 +24,11 @@
  *     (0,0,0); isotropic voxel size.  Voxel (x, y, z) has linear index
  *     x + nx (y + ny z) and covers [x, x+1) x [y, y+1) x [z, z+1) in voxel units.
  *   - Accumulators (caller-owned device memory, usv_accumulator_bytes bytes):
- *     uint32 sum[nvox] followed by uint16 cnt[nvox rounded up to even].
+ *     uint32 sum[nvox] followed by uint16 cnt[nvox rounded up to even].  The library
+ *     tracks the box of voxels its ingest calls may have changed since the last reset:
+ *     usv_reset zeroes only that box and usv_finalize reads only that box (dilated by
+ *     one); everything outside it is taken to be zero.  A caller that writes the buffer
+ *     itself hands it over with usv_import_accumulators (or clears it with usv_reset).
  *   - Every call is ordered on the stream given to usv_create_volume (a hipStream_t
  *     passed as void*; NULL = the default stream) and is asynchronous unless noted.
  *     Device buffers belong to the caller; the library owns only the opaque objects,

@@ -65,6 +65,23 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
   const int64_t nxy = (int64_t)a.nx * a.ny;
   const int x = x0 + tx;
   const bool xin = x < a.nx;
+  // a block whose outputs all lie outside the live box (every accumulator there and in
+  // its halo is zero, so every output is 0 / EMPTY) writes zeros without reading
+  if (x0 >= a.live_hi[0] || x0 + TX <= a.live_lo[0] || y0 >= a.live_hi[1] || y0 + TY <= a.live_lo[1] ||
+      zs >= a.live_hi[2] || ze <= a.live_lo[2]) {
+    if (!xin || x >= a.hi[0]) return;
+    for (int z = zs; z < ze; ++z) {
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        const int y = y0 + wv * RPW + k;
+        if (y >= a.hi[1]) continue;
+        const int64_t i = nxy * z + (int64_t)a.nx * y + x;
+        a.V[i] = 0;
+        if (a.state) a.state[i] = 0;
+      }
+    }
+    return;
+  }
   // per-lane 32-bit offsets inside a plane (grids hold < 2^31 voxels); plane bases are uniform
   uint32_t off[RPW];
   uint32_t own = 0u;   // bit k: voxel k of this lane is in the grid

@@ -77,6 +77,9 @@ struct usv_volume {
   size_t d_batch_bytes = 0;
   StagingRing batch_stage;
   uint32_t *d_counter = nullptr;
+  // voxel box outside which every accumulator is zero (empty after a reset; the whole
+  // grid at creation and after an import)
+  usv_box touched{};
   // overlapped ingest (usv_set_ingest_overlap): launches alternate between two library
   // streams that wait for `stream` at each launch; `stream` waits for them lazily
   bool overlap = false;
@@ -268,6 +271,22 @@ usv_box empty_box() {
     b.hi[a] = 0;
   }
   return b;
+}
+
+bool box_empty(const usv_box &b) { return b.lo[0] >= b.hi[0] || b.lo[1] >= b.hi[1] || b.lo[2] >= b.hi[2]; }
+
+usv_box grid_box(const usv_volume *v) {
+  usv_box b;
+  b.lo[0] = b.lo[1] = b.lo[2] = 0;
+  b.hi[0] = v->nx;
+  b.hi[1] = v->ny;
+  b.hi[2] = v->nz;
+  return b;
+}
+
+// Widen the touched box by a box some ingest may change (called before the launch).
+void touch(usv_volume *v, const usv_box &b) {
+  if (!box_empty(b)) box_union(v->touched, b.lo, b.hi);
 }
 
 // ---- tiling --------------------------------------------------------------------------
@@ -521,6 +540,7 @@ usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *s
     usv_destroy_volume(v);
     return USV_E_OOM;
   }
+  v->touched = grid_box(v);   // the caller's buffer holds anything until the first reset
   usv_status st = usv_reset(v);
   if (st != USV_OK) {
     usv_destroy_volume(v);
@@ -537,9 +557,20 @@ usv_status usv_reset(usv_volume *v) {
     usv_status js = join_side(v);
     if (js != USV_OK) return js;
   }
-  const int64_t words = (int64_t)(usv_accumulator_bytes_of(v) / 4);
-  usv_status st = check_hip(v, launch_zero_u32((uint32_t *)v->acc, words, v->stream), "zero accumulators");
+  // only the touched box can hold non-zero accumulators
+  usv_status st = USV_OK;
+  const usv_box full = grid_box(v);
+  const usv_box &t = v->touched;
+  if (t.lo[0] == 0 && t.lo[1] == 0 && t.lo[2] == 0 && t.hi[0] == full.hi[0] && t.hi[1] == full.hi[1] &&
+      t.hi[2] == full.hi[2]) {
+    const int64_t words = (int64_t)(usv_accumulator_bytes_of(v) / 4);
+    st = check_hip(v, launch_zero_u32((uint32_t *)v->acc, words, v->stream), "zero accumulators");
+  } else if (!box_empty(t)) {
+    st = check_hip(v, launch_zero_box(v->sum, (uint16_t *)v->cnt32, v->nx, v->ny, t.lo, t.hi, v->stream),
+                   "zero accumulators");
+  }
   if (st != USV_OK) return st;
+  v->touched = empty_box();
   v->count_dirty = false;
   return check_hip(v, launch_zero_u32(v->d_err, (int64_t)(kStatusBytes / 4), v->stream), "zero status");
 }
@@ -657,6 +688,7 @@ usv_status usv_import_accumulators(usv_volume *v, const void *src) {
     usv_status js = join_side(v);
     if (js != USV_OK) return js;
   }
+  v->touched = grid_box(v);   // imported content may be anywhere
   usv_status st = check_hip(v, launch_copy_u32((uint32_t *)v->acc, (const uint32_t *)src,
                                                (int64_t)(usv_accumulator_bytes_of(v) / 4), v->stream), "import");
   if (st != USV_OK) return st;
@@ -731,11 +763,11 @@ usv_status usv_ingest_frames(usv_volume *v, int32_t probe_id, const uint8_t *fra
   if (n == 0) return USV_OK;
   std::vector<float> maps, smaps;
   std::vector<int32_t> fidx, sfidx;
-  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, dirty_out, &smaps, &sfidx);
-  if (st != USV_OK) {
-    if (dirty_out) *dirty_out = empty_box();
-    return st;
-  }
+  usv_box box = empty_box();
+  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, &box, &smaps, &sfidx);
+  if (st != USV_OK) return st;
+  if (dirty_out) *dirty_out = box;
+  touch(v, box);
   v->count_dirty = true;
   st = launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx);
   if (st != USV_OK || sfidx.empty()) return st;
@@ -757,11 +789,11 @@ usv_status usv_ingest_frames_cut(usv_volume *v, int32_t probe_id, const uint8_t 
   std::vector<float> maps, smaps;
   std::vector<int32_t> fidx, sfidx;
   std::vector<uint32_t> rk, srk;
-  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, dirty_out, &smaps, &sfidx, rows, &rk, &srk);
-  if (st != USV_OK) {
-    if (dirty_out) *dirty_out = empty_box();
-    return st;
-  }
+  usv_box box = empty_box();
+  usv_status st = prepare_frames(v, p, poses, n, maps, fidx, &box, &smaps, &sfidx, rows, &rk, &srk);
+  if (st != USV_OK) return st;
+  if (dirty_out) *dirty_out = box;
+  touch(v, box);
   v->count_dirty = true;
   st = launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx, false, &rk);
   if (st != USV_OK || sfidx.empty()) return st;
@@ -797,7 +829,27 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
       a.hi[k] = dims[k];
     }
   }
+  // voxels that can be non-zero after the fill: the touched box dilated by one
+  for (int k = 0; k < 3; ++k) {
+    if (box_empty(v->touched)) {
+      a.live_lo[k] = 0;
+      a.live_hi[k] = 0;
+    } else {
+      a.live_lo[k] = std::max(0, v->touched.lo[k] - 1);
+      a.live_hi[k] = std::min(dims[k], v->touched.hi[k] + 1);
+    }
+  }
   a.zchunk = 16;   // measured on the whole-spine grid: 16 planes 0.266 ms, 32 planes 0.279 ms, 64 planes 0.302 ms
+  // outputs outside the live box are 0 / EMPTY: written by a plain fill; the stencil
+  // kernel runs over the output box clipped to the live box only
+  usv_status st = check_hip(v, launch_fill_outside(vol_u8, state, v->nx, v->ny, a.lo, a.hi, a.live_lo, a.live_hi,
+                                                   v->stream), "finalize fill");
+  if (st != USV_OK) return st;
+  for (int k = 0; k < 3; ++k) {
+    a.lo[k] = std::max(a.lo[k], a.live_lo[k]);
+    a.hi[k] = std::min(a.hi[k], a.live_hi[k]);
+    if (a.lo[k] >= a.hi[k]) return USV_OK;
+  }
   return check_hip(v, launch_finalize(a, v->stream), "finalize launch");
 }
 
@@ -1001,14 +1053,17 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
     if (n_frames[i] == 0) continue;
     usv_volume *v = vols[i];
     const size_t e = 2 * (size_t)i;
+    usv_box box = empty_box();
     usv_status st = prepare_frames(v, v->probes[(size_t)probe_ids[i]], poses[i], n_frames[i], maps[e], fidx[e],
-                                   dirty_out ? &dirty_out[i] : nullptr, &maps[e + 1], &fidx[e + 1]);
+                                   &box, &maps[e + 1], &fidx[e + 1]);
     if (st != USV_OK) {
       if (dirty_out)
         for (int32_t j = 0; j < n_sweeps; ++j) dirty_out[j] = empty_box();
       owner->last_error = v->last_error;
       return st;
     }
+    if (dirty_out) dirty_out[i] = box;
+    touch(v, box);
   }
   // table layout: BatchSweep[n] | maps | fidx
   size_t off_maps = align_up(sizeof(BatchSweep) * (size_t)n_sweeps * 2, 256);
@@ -1286,6 +1341,7 @@ usv_status usv_graph_launch(usv_graph *g, const uint8_t *frame_host, const doubl
   int lo[3], hi[3];
   if (!frame_box(M, p.W, p.H, dims, lo, hi)) return USV_OK;
   if (dirty_out) box_union(*dirty_out, lo, hi);
+  box_union(v->touched, lo, hi);
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   const int k = g->next;
   if (g->used[k]) {

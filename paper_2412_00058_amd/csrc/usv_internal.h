@@ -93,6 +93,12 @@ hipError_t launch_zero_u32(uint32_t *p, int64_t n_words, hipStream_t s);
 hipError_t launch_count_check(const uint32_t *cnt32, int64_t n_words, unsigned long long *kept,
                               unsigned long long *partials, uint32_t *err, bool store, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n_words, hipStream_t s);
+// Zero sum[] and the uint16 counts of the voxel box [lo, hi) of an nx x ny x nz grid.
+hipError_t launch_zero_box(uint32_t *sum, uint16_t *cnt, int nx, int ny, const int lo[3], const int hi[3],
+                           hipStream_t s);
+// V = 0 (and state = 0 if non-null) over the box [o_lo, o_hi) minus the box [l_lo, l_hi).
+hipError_t launch_fill_outside(uint8_t *V, uint8_t *S, int nx, int ny, const int o_lo[3], const int o_hi[3],
+                               const int l_lo[3], const int l_hi[3], hipStream_t s);
 
 // ---- finalize ----------------------------------------------------------------------------
 
@@ -104,6 +110,7 @@ struct FinalizeArgs {
   int32_t nx, ny, nz;
   int32_t fill_min;
   int32_t lo[3], hi[3];  // output box [lo, hi) (already dilated and clipped)
+  int32_t live_lo[3], live_hi[3];   // outside this box every accumulator is zero
   int32_t zchunk;
   int32_t gx, gy, gz, bands_per_xcd;   // block grid (set by launch_finalize)
 };

@@ -292,3 +292,52 @@ def test_new_entry_points_edge_cases():
     V, _ = gpu_volume(g).finalize()
     with pytest.raises(UsvError):
         extract_slices(V, 2, g.dims[2] - 1, 2)
+
+
+def test_touched_box_reset_and_finalize():
+    """Reset zeroes only the box that ingest could have touched and finalize reads only
+    that box: outputs pre-filled with garbage are fully overwritten, a reset after a
+    partial ingest leaves all accumulators zero, and an import makes the whole grid live
+    again."""
+    say("case: touched box")
+    d = synth.cfg1()
+    g = d["grid"]
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    fr = to_dev(d["frames"])
+    nx, ny, nz = g.dims
+    V = torch.full((nz, ny, nx), 0xAB, dtype=torch.uint8, device="cuda")
+    S = torch.full_like(V, 0xCD)
+    vol.finalize(out=(V, S))          # nothing touched: all zero / EMPTY, without reading
+    vol.sync()
+    assert not V.any() and not S.any()
+    vol.ingest(pid, fr[:10], d["poses"][:10])
+    V.fill_(0xAB)
+    S.fill_(0xCD)
+    vol.finalize(out=(V, S))
+    vol.sync()
+    acc = oracle.Accum(g)
+    acc.ingest(d["frames"][:10], d["poses"][:10], d["probe"])
+    Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    vol.reset()
+    vol.sync()
+    assert not vol.acc.any()
+    # an imported block (content anywhere) is read in full and cleared in full
+    rng = np.random.default_rng(3)
+    raw = np.zeros(vol.acc.numel() * 4, np.uint8)
+    s = np.zeros(g.nvox, np.uint32)
+    c = np.zeros(g.nvox, np.uint16)
+    m = rng.random(g.nvox) < 0.01
+    c[m] = rng.integers(1, 9, m.sum())
+    s[m] = c[m].astype(np.uint32) * rng.integers(0, 256, m.sum()).astype(np.uint32)
+    raw[: 4 * g.nvox] = s.view(np.uint8)
+    raw[4 * g.nvox: 6 * g.nvox] = c.view(np.uint8)
+    vol.import_accumulators(torch.from_numpy(raw.view(np.int32)).cuda())
+    V2, S2 = vol.finalize()
+    vol.sync()
+    Vo, So, _ = oracle.finalize(g, s, c)
+    assert np.array_equal(V2.cpu().numpy(), Vo) and np.array_equal(S2.cpu().numpy(), So)
+    vol.reset()
+    vol.sync()
+    assert not vol.acc.any()
