@@ -3,7 +3,8 @@
 //   - no-return 32/64-bit global atomic adds per second when each wave instruction covers
 //     runs of R consecutive words at random 128-byte-aligned places of a 645 MB buffer
 //     (the accumulator size of the whole-spine grid), R = 1 .. 16, and the rate of
-//     distinct 64-byte segments per instruction ("requests");
+//     distinct 64-byte segments per instruction ("requests"); the same with workgroup,
+//     agent and system memory scope, and on 2 / 16 / 128 MB footprints;
 //   - read bandwidth of a grid-stride streaming kernel;
 //   - time per back-to-back launch of an empty kernel.
 // Build: hipcc --offload-arch=gfx950 -O3 -o microbench/atomic_rate microbench/atomic_rate.hip
@@ -31,6 +32,18 @@ __global__ __launch_bounds__(256) void atomic_runs(T *base, uint32_t nlines, int
   for (int it = 0; it < iters; ++it) {
     const uint32_t h = (wave * 64 + run + it * 7919u) * 2654435761u;
     atomicAdd(base + (uint64_t)(h % nlines) * per_line + off, (T)1);
+  }
+}
+
+
+template <class T, int SCOPE>
+__global__ __launch_bounds__(256) void atomic_runs_scoped(T *base, uint32_t nlines, int R, int iters) {
+  const uint32_t lane = threadIdx.x & 63, wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t run = lane / R, off = lane - run * R;
+  const uint32_t per_line = 128 / sizeof(T);
+  for (int it = 0; it < iters; ++it) {
+    const uint32_t h = (wave * 64 + run + it * 7919u) * 2654435761u;
+    (void)__hip_atomic_fetch_add(base + (uint64_t)(h % nlines) * per_line + off, (T)1, __ATOMIC_RELAXED, SCOPE);
   }
 }
 
@@ -81,6 +94,40 @@ int main() {
     rate = n_atomics * reps / (ms * 1e-3);
     std::printf("  u32 runs of %2d: %7.1f G atomics/s  %6.1f G 64-byte requests/s\n", R, rate / 1e9,
                 rate * ((R * 4 + 63) / 64) / R / 1e9);
+  }
+
+  for (int R : {1, 4, 16}) {
+    for (int sc = 0; sc < 3; ++sc) {
+      auto run = [&]() {
+        if (sc == 0) atomic_runs_scoped<unsigned long long, __HIP_MEMORY_SCOPE_WORKGROUP><<<blocks, 256>>>((unsigned long long *)buf, nlines, R, iters);
+        else if (sc == 1) atomic_runs_scoped<unsigned long long, __HIP_MEMORY_SCOPE_AGENT><<<blocks, 256>>>((unsigned long long *)buf, nlines, R, iters);
+        else atomic_runs_scoped<unsigned long long, __HIP_MEMORY_SCOPE_SYSTEM><<<blocks, 256>>>((unsigned long long *)buf, nlines, R, iters);
+      };
+      for (int w = 0; w < 3; ++w) run();
+      CK(hipEventRecord(e0));
+      for (int r = 0; r < reps; ++r) run();
+      CK(hipEventRecord(e1));
+      CK(hipEventSynchronize(e1));
+      CK(hipEventElapsedTime(&ms, e0, e1));
+      double rate = n_atomics * reps / (ms * 1e-3);
+      std::printf("  scope %s u64 runs of %2d: %7.1f G atomics/s  %6.1f G 64-byte requests/s\n",
+                  sc == 0 ? "workgroup" : (sc == 1 ? "agent    " : "system   "), R, rate / 1e9,
+                  rate * ((R * 8 + 63) / 64) / R / 1e9);
+    }
+  }
+  for (uint64_t small : {2ull << 20, 16ull << 20, 128ull << 20}) {
+    const uint32_t nl = (uint32_t)(small / 128) - 1;
+    for (int R : {1, 16}) {
+      for (int w = 0; w < 3; ++w) atomic_runs<unsigned long long><<<blocks, 256>>>((unsigned long long *)buf, nl, R, iters);
+      CK(hipEventRecord(e0));
+      for (int r = 0; r < reps; ++r) atomic_runs<unsigned long long><<<blocks, 256>>>((unsigned long long *)buf, nl, R, iters);
+      CK(hipEventRecord(e1));
+      CK(hipEventSynchronize(e1));
+      CK(hipEventElapsedTime(&ms, e0, e1));
+      double rate = n_atomics * reps / (ms * 1e-3);
+      std::printf("  %4llu MB buffer, u64 runs of %2d: %7.1f G atomics/s  %6.1f G 64-byte requests/s\n",
+                  (unsigned long long)(small >> 20), R, rate / 1e9, rate * ((R * 8 + 63) / 64) / R / 1e9);
+    }
   }
   const int64_t n16 = (int64_t)(bytes / 16);
   for (int w = 0; w < 3; ++w) stream_read<<<8192, 256>>>((const uint4 *)buf, n16, out);
