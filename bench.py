@@ -83,9 +83,9 @@ def time_oracle_step(d, seg, min_seconds=10.0, max_reps=3):
     return total / reps, reps
 
 
-def traffic_from_profile(src_hash, tile):
-    """HBM traffic per ingest launch from the committed rocprofv3 counter summary, if it was
-    taken on the current ingest kernel source with the same tile shape; otherwise None."""
+def counters_record(src_hash, tile):
+    """The committed rocprofv3 counter summary of the ingest kernel, if it was taken on the
+    current ingest kernel source with the same tile shape; otherwise None."""
     p = os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json")
     try:
         rec = json.load(open(p))
@@ -93,7 +93,12 @@ def traffic_from_profile(src_hash, tile):
         return None
     if rec.get("ingest_source_sha256") != src_hash or rec.get("tile") != list(tile):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+# device-scope atomic requests (64-byte segments per wave instruction) per second on the
+# MI355X, measured by microbench/atomic_rate (profiles/atomics_microbench.txt): 21.6-26.7 G
+ATOMIC_REQ_RATE = 23.0e9
 
 
 def counters_summary(fetch_db, write_db, out_json, atomic_db=None, tile=None):
@@ -605,14 +610,22 @@ def main():
     # distinct voxels are counted per 64-frame call; with smaller launches this undercounts
     # the accumulator bytes (a conservative roofline)
     achieved = alg_bytes / n_kernel / (per_launch_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(ingest_source_hash(), tile)
+    rec = counters_record(ingest_source_hash(), tile)
+    traffic = rec.get("hbm_bytes_per_launch") if rec else None
+    atomic = None
+    if rec and rec.get("atomic_requests_per_launch"):
+        floor_ms = rec["atomic_requests_per_launch"] / ATOMIC_REQ_RATE * 1e3
+        atomic = {"requests_per_launch": rec["atomic_requests_per_launch"], "rate_per_s": ATOMIC_REQ_RATE,
+                  "floor_ms": round(floor_ms, 5), "frac": round(floor_ms / per_launch_ms, 4),
+                  "frac_overlapped": round(floor_ms / overlapped_launch_ms, 4)}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ingest_kernel (PNN scatter, %d frames per launch)" % frames_per_launch,
             "alg_bytes_per_launch": int(alg_bytes / n_kernel), "launch_ms": round(per_launch_ms, 5),
             "distinct_voxels_per_launch": int(U / n_kernel),
             "overlapped": {"ingest_phase_ms": round(phase[0], 4), "ms_per_launch": round(overlapped_launch_ms, 5),
-                           "achieved": round(alg_bytes / n_kernel / (overlapped_launch_ms * 1e-3) / 1e9, 1)}}
+                           "achieved": round(alg_bytes / n_kernel / (overlapped_launch_ms * 1e-3) / 1e9, 1)},
+            "atomic_request_floor": atomic}
 
     extras = {}
     if not args.no_extras:
