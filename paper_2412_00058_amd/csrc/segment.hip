@@ -34,13 +34,20 @@ __host__ __forceinline__ unsigned xcd_blocks(int gx, int nbands) { return (unsig
 // needs nx % 4 == 0 and a 4-byte aligned volume; else 1).  K: the window length k when it
 // is 1 .. kUnroll (the row leaving the window is then in a batch already loaded), 0 for
 // any k (that row is loaded again).
+//
+// Lanes are numbered over all (z, column group) pairs, column group fastest, 64 per block,
+// so no lane idles at a row's end and a launch holds exactly as many waves as the grid
+// needs (a wave whose lanes cross into the next plane still reads two contiguous runs).
 template <int kC, int K>
 __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
   __shared__ int32_t best_s_sh[kSeg][64][kC], best_y_sh[kSeg][64][kC];
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
-  int bx, z;
-  if (!xcd_block((a.nx + 64 * kC - 1) / (64 * kC), a.nz, bx, z)) return;   // uniform per block
-  const int x = (bx * 64 + lane) * kC;   // first column of this lane
+  const uint32_t groups = (uint32_t)(a.nx / kC), total = groups * (uint32_t)a.nz;   // < 2^31
+  int bx, band;
+  if (!xcd_block(1, (int)((total + 63u) / 64u), bx, band)) return;   // uniform per block
+  const uint32_t gl = (uint32_t)band * 64u + (uint32_t)lane;
+  const int z = gl < total ? (int)(gl / groups) : 0;
+  const int x = gl < total ? (int)(gl - (uint32_t)z * groups) * kC : a.nx;   // first column of this lane
   const int ymax = a.ny - 1 - a.k;
   int best[kC], best_s[kC];
 #pragma unroll
@@ -301,9 +308,9 @@ void launch_contour_k(const SegArgs &a, dim3 grid, hipStream_t s) {
 hipError_t launch_contour(const SegArgs &a, hipStream_t s) {
   static_assert(kUnroll == 8, "the k dispatch covers 1 .. kUnroll");
   if (a.nx % 4 == 0 && a.row_pitch % 4 == 0 && a.plane_pitch % 4 == 0 && (((uintptr_t)a.V) & 3u) == 0)
-    launch_contour_k<4>(a, dim3(xcd_blocks((a.nx + 255) / 256, a.nz)), s);
+    launch_contour_k<4>(a, dim3(xcd_blocks(1, (int)(((int64_t)(a.nx / 4) * a.nz + 63) / 64))), s);
   else
-    launch_contour_k<1>(a, dim3(xcd_blocks((a.nx + 63) / 64, a.nz)), s);
+    launch_contour_k<1>(a, dim3(xcd_blocks(1, (int)(((int64_t)a.nx * a.nz + 63) / 64))), s);
   return hipGetLastError();
 }
 
