@@ -82,14 +82,17 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
     }
     return;
   }
+  // Only voxels that an output reads are loaded: x in [lo - 1, hi], y likewise, planes
+  // zs - 1 .. ze (the last block of a row or band and the look-ahead past ze would
+  // otherwise fetch columns, rows and planes no output uses); the rest count as 0.
   // per-lane 32-bit offsets inside a plane (grids hold < 2^31 voxels); plane bases are uniform
   uint32_t off[RPW];
-  uint32_t own = 0u;   // bit k: voxel k of this lane is in the grid
+  uint32_t own = 0u;   // bit k: voxel k of this lane is loaded
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int y = y0 + wv * RPW + k;
     off[k] = (uint32_t)x + (uint32_t)a.nx * (uint32_t)y;
-    if (xin && y < a.ny) own |= 1u << k;
+    if (xin && x <= a.hi[0] && y < a.ny && y <= a.hi[1]) own |= 1u << k;
   }
   // this lane's halo voxel (plane coordinates): left / right columns, then top / bottom rows
   int hpx = -1, hpy = -1;
@@ -102,13 +105,13 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
     hpy = e < TX ? 0 : PY - 1;
   }
   const int hx = x0 - 1 + hpx, hy = y0 - 1 + hpy;
-  const bool hin = hpx >= 0 && hx >= 0 && hx < a.nx && hy >= 0 && hy < a.ny;
+  const bool hin = hpx >= 0 && hx >= 0 && hx < a.nx && hx <= a.hi[0] && hy >= 0 && hy < a.ny && hy <= a.hi[1];
   const uint32_t hoff = hin ? (uint32_t)hx + (uint32_t)a.nx * (uint32_t)hy : 0u;
 
   // loads are unconditional (out-of-grid lanes read voxel 0 of the plane) and masked
   // afterwards: no branches around them
   auto load = [&](int z, Raw &r) {
-    const bool zin = z >= 0 && z < a.nz;
+    const bool zin = z >= 0 && z < a.nz && z <= ze;
     const uint32_t m = zin ? own : 0u;
     const uint32_t hm = (zin && hin) ? ~0u : 0u;
     const char *ps = reinterpret_cast<const char *>(a.sum + (zin ? nxy * z : 0));
