@@ -1,8 +1,9 @@
 // Zero and copy of 32-bit word buffers (accumulator reset, export / import, scratch
 // clears), the zeroing of one voxel box of the accumulators, and the zero outputs of
-// finalize outside the box where accumulators can be non-zero.  Both are plain streams: 16-byte stores (and loads) per lane where the
-// buffers allow it, so a wave moves 1 KiB per instruction; the unaligned head and the
-// tail go word by word.
+// finalize outside the box where accumulators can be non-zero.  All are plain streams:
+// 16-byte stores (and loads) per lane where the buffers allow it, so a wave moves 1 KiB
+// per instruction; unaligned heads and tails go word by word (byte by byte for the
+// finalize outputs).
 #include "usv_internal.h"
 
 namespace usv {
@@ -46,67 +47,54 @@ __global__ __launch_bounds__(256) void zero_box_kernel(uint32_t *__restrict__ su
   }
 }
 
-// Zero bytes [start, end) of p with `lanes` threads (thread index t): bytes up to a
-// 16-byte boundary, then 16-byte stores, then the remaining bytes.
-__device__ __forceinline__ void zero_bytes(uint8_t *p, int64_t start, int64_t end, int t, int lanes) {
-  if (end <= start) return;
-  const uintptr_t base = (uintptr_t)p;
-  int64_t a16 = (int64_t)((((base + start) + 15) & ~(uintptr_t)15) - base);
-  if (a16 > end) a16 = end;
-  int64_t b16 = (int64_t)(((base + end) & ~(uintptr_t)15) - base);
-  if (b16 < a16) b16 = a16;
-  for (int64_t i = start + t; i < a16; i += lanes) p[i] = 0;
-  for (int64_t i = a16 + 16 * (int64_t)t; i < b16; i += 16 * (int64_t)lanes)
-    *reinterpret_cast<uint4 *>(p + i) = make_uint4(0u, 0u, 0u, 0u);
-  for (int64_t i = b16 + t; i < end; i += lanes) p[i] = 0;
+struct FillOutsideArgs {
+  uint8_t *V, *S;         // outputs (S may be null)
+  int nx, ny;
+  int o_lo[3], o_hi[3];   // output box
+  int l_lo[3], l_hi[3];   // live box (all zero: none)
+  int ey;                 // rows of the output box per plane
+  uint32_t cpr, m_cpr, m_ey, total;   // chunks per row, division magics, threads
+};
+
+// n / d for n < 2^32, given m = floor(2^32 / d) (2^32 - 1 for d = 1): umulhi(n, m) is
+// the quotient or one below it.
+__device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t d, uint32_t m) {
+  uint32_t q = __umulhi(n, m);
+  if (n - q * d >= d) ++q;
+  return q;
 }
 
-// V = 0 and state = 0 over the output box [o_lo, o_hi) minus the live box [l_lo, l_hi),
-// eight blocks per z plane of the output box.  Rows wholly outside the live box are zeroed
-// by the whole block (as one span when the box spans whole rows); rows that cross it lose
-// their two end segments, one wave per row.
-__global__ __launch_bounds__(256) void fill_outside_kernel(uint8_t *__restrict__ V, uint8_t *__restrict__ S, int nx,
-                                                           int ny, int3 o_lo, int3 o_hi, int3 l_lo, int3 l_hi) {
-  const int z = o_lo.z + (int)blockIdx.x;
-  const int t = threadIdx.x, lane = t & 63;
-  const int parts = (int)gridDim.y, part_id = (int)blockIdx.y;   // blocks sharing the plane
-  const int wv = (t >> 6) + 4 * part_id, nwv = 4 * parts;          // this wave among the plane's waves
-  const bool in_z = z >= l_lo.z && z < l_hi.z;
-  const bool whole_rows = o_lo.x == 0 && o_hi.x == nx;
-  const int64_t plane = (int64_t)nx * ny * z;
-  // rows wholly outside: [o_lo.y, ya) and [yb, o_hi.y)
-  const int ya = in_z ? max(o_lo.y, min(l_lo.y, o_hi.y)) : o_hi.y;
-  const int yb = in_z ? min(o_hi.y, max(l_hi.y, ya)) : o_hi.y;
-  const bool x_gap = !(l_lo.x <= o_lo.x && l_hi.x >= o_hi.x);   // crossing rows keep some outside part
-  for (int part = 0; part < 2; ++part) {
-    const int y0 = part ? yb : o_lo.y, y1 = part ? o_hi.y : ya;
-    if (y1 <= y0) continue;
-    if (whole_rows) {
-      // the span split evenly over the plane's blocks (split points on 16-byte steps)
-      const int64_t s0 = plane + (int64_t)nx * y0, s1 = plane + (int64_t)nx * y1;
-      const int64_t step = (((s1 - s0) / parts) + 15) & ~(int64_t)15;
-      const int64_t a0 = min(s1, s0 + step * part_id), a1 = min(s1, a0 + step);
-      zero_bytes(V, a0, a1, t, 256);
-      if (S) zero_bytes(S, a0, a1, t, 256);
-    } else {
-      for (int y = y0 + wv; y < y1; y += nwv) {
-        const int64_t a0 = plane + (int64_t)nx * y + o_lo.x, a1 = plane + (int64_t)nx * y + o_hi.x;
-        zero_bytes(V, a0, a1, lane, 64);
-        if (S) zero_bytes(S, a0, a1, lane, 64);
-      }
-    }
+// V = 0 (blockIdx.y = 0) or state = 0 (blockIdx.y = 1) over the output box minus the live
+// box.  Threads are numbered over (row of the output box, 16-byte chunk of that row), the
+// chunks counted from the 16-byte boundary at or below the row's first byte of the array
+// (so both arrays take whole 16-byte stores whatever their alignment): a chunk wholly
+// outside the live box and inside the row's output span is one 16-byte store, a chunk
+// cut by an edge of either box goes byte by byte, a chunk inside the live box is skipped.
+__global__ __launch_bounds__(256) void fill_outside_kernel(FillOutsideArgs a) {
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= a.total) return;
+  uint8_t *p = blockIdx.y ? a.S : a.V;
+  const uint32_t r = div_magic(t, a.cpr, a.m_cpr), k = t - r * a.cpr;
+  const uint32_t zr = div_magic(r, (uint32_t)a.ey, a.m_ey);
+  const int y = a.o_lo[1] + (int)(r - zr * (uint32_t)a.ey), z = a.o_lo[2] + (int)zr;
+  const int64_t row = ((int64_t)z * a.ny + y) * a.nx;
+  const int64_t a0 = row + a.o_lo[0], a1 = row + a.o_hi[0];   // output bytes of the row
+  const uintptr_t pb = (uintptr_t)p;
+  const int64_t c = (int64_t)(((pb + (uintptr_t)a0) & ~(uintptr_t)15) - pb) + 16 * (int64_t)k;
+  if (c >= a1) return;
+  int64_t b0 = 0, b1 = 0;   // live bytes of the row (none: an empty range)
+  if (y >= a.l_lo[1] && y < a.l_hi[1] && z >= a.l_lo[2] && z < a.l_hi[2]) {
+    b0 = row + a.l_lo[0];
+    b1 = row + a.l_hi[0];
   }
-  if (!x_gap) return;
-  for (int y = ya + wv; y < yb; y += nwv) {
-    const int64_t row = plane + (int64_t)nx * y;
-    const int64_t a0 = row + o_lo.x, a1 = row + max(o_lo.x, min(l_lo.x, o_hi.x));
-    const int64_t b0 = row + min(o_hi.x, max(l_hi.x, o_lo.x)), b1 = row + o_hi.x;
-    zero_bytes(V, a0, a1, lane, 64);
-    zero_bytes(V, b0, b1, lane, 64);
-    if (S) {
-      zero_bytes(S, a0, a1, lane, 64);
-      zero_bytes(S, b0, b1, lane, 64);
-    }
+  if (c >= b0 && c + 16 <= b1) return;
+  if (c >= a0 && c + 16 <= a1 && (c + 16 <= b0 || c >= b1)) {
+    *reinterpret_cast<uint4 *>(p + c) = make_uint4(0u, 0u, 0u, 0u);
+    return;
+  }
+  for (int i = 0; i < 16; ++i) {
+    const int64_t e = c + i;
+    if (e >= a0 && e < a1 && (e < b0 || e >= b1)) p[e] = 0;
   }
 }
 
@@ -139,11 +127,32 @@ hipError_t launch_zero_box(uint32_t *sum, uint16_t *cnt, int nx, int ny, const i
 
 hipError_t launch_fill_outside(uint8_t *V, uint8_t *S, int nx, int ny, const int o_lo[3], const int o_hi[3],
                                const int l_lo[3], const int l_hi[3], hipStream_t s) {
-  const int ey = o_hi[1] - o_lo[1], ez = o_hi[2] - o_lo[2];
-  if (o_hi[0] <= o_lo[0] || ey <= 0 || ez <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_outside_kernel, dim3((unsigned)ez, 8), dim3(256), 0, s, V, S, nx, ny,
-                     make_int3(o_lo[0], o_lo[1], o_lo[2]), make_int3(o_hi[0], o_hi[1], o_hi[2]),
-                     make_int3(l_lo[0], l_lo[1], l_lo[2]), make_int3(l_hi[0], l_hi[1], l_hi[2]));
+  const int ex = o_hi[0] - o_lo[0], ey = o_hi[1] - o_lo[1], ez = o_hi[2] - o_lo[2];
+  if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
+  FillOutsideArgs a{};
+  a.V = V;
+  a.S = S;
+  a.nx = nx;
+  a.ny = ny;
+  a.ey = ey;
+  bool live = true;
+  for (int k = 0; k < 3; ++k) {
+    a.o_lo[k] = o_lo[k];
+    a.o_hi[k] = o_hi[k];
+    a.l_lo[k] = l_lo[k];
+    a.l_hi[k] = l_hi[k];
+    live = live && l_lo[k] < l_hi[k];
+  }
+  if (!live)
+    for (int k = 0; k < 3; ++k) a.l_lo[k] = a.l_hi[k] = 0;   // no live row
+  a.cpr = (uint32_t)((ex + 15) / 16 + 1);   // chunks a row of ex bytes can touch
+  // rows * cpr <= 2 * voxels < 2^32 for grids of fewer than 2^31 voxels
+  const uint64_t total = (uint64_t)ey * (uint64_t)ez * a.cpr;
+  if (total >= ((uint64_t)1 << 32)) return hipErrorInvalidValue;
+  a.total = (uint32_t)total;
+  a.m_cpr = (uint32_t)(((uint64_t)1 << 32) / a.cpr);
+  a.m_ey = ey == 1 ? 0xFFFFFFFFu : (uint32_t)(((uint64_t)1 << 32) / (uint64_t)ey);
+  hipLaunchKernelGGL(fill_outside_kernel, dim3((unsigned)((total + 255) / 256), S ? 2 : 1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -341,3 +341,55 @@ def test_touched_box_reset_and_finalize():
     vol.reset()
     vol.sync()
     assert not vol.acc.any()
+
+
+@pytest.mark.parametrize("offsets", [(1, 5), (8, 0), (3, None)])
+def test_finalize_outputs_at_any_alignment(offsets):
+    """Finalize into outputs that start at odd byte offsets (and without the state
+    array): the zero fill outside the live box and the stencil inside it write exactly the
+    output box, whole volume or a region, nothing before or after it."""
+    from paper_2412_00058_amd import Box
+    say("case: finalize output offsets", offsets)
+    d = synth.cfg1()
+    g = d["grid"]
+    nx, ny, nz = g.dims
+    n = g.nvox
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    fr = to_dev(d["frames"])
+    vol.ingest(pid, fr[:24], d["poses"][:24])
+    acc = oracle.Accum(g)
+    acc.ingest(d["frames"][:24], d["poses"][:24], d["probe"])
+    Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+    ov, os_ = offsets
+    bufV = torch.full((n + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+    bufS = torch.full((n + 64,), 0xCD, dtype=torch.uint8, device="cuda")
+    V = bufV[ov:ov + n].view(nz, ny, nx)
+    S = bufS[os_:os_ + n].view(nz, ny, nx) if os_ is not None else None
+    vol.finalize(out=(V, S))
+    vol.sync()
+    assert np.array_equal(V.cpu().numpy(), Vo)
+    if S is not None:
+        assert np.array_equal(S.cpu().numpy(), So)
+        assert (bufS[:os_] == 0xCD).all() and (bufS[os_ + n:] == 0xCD).all()
+    assert (bufV[:ov] == 0xAB).all() and (bufV[ov + n:] == 0xAB).all()
+    # a region finalize rewrites the region grown by one voxel and nothing else
+    box = Box()
+    box.lo[:] = (3, 2, 5)
+    box.hi[:] = (nx - 7, ny - 1, nz - 9)
+    V.fill_(0x11)
+    if S is not None:
+        S.fill_(0x22)
+    vol.finalize(region=box, out=(V, S))
+    vol.sync()
+    lo = [max(0, box.lo[k] - 1) for k in range(3)]
+    hi = [min(g.dims[k], box.hi[k] + 1) for k in range(3)]
+    sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    inside = np.zeros((nz, ny, nx), bool)
+    inside[sl] = True
+    Vg = V.cpu().numpy()
+    assert np.array_equal(Vg[inside], Vo[inside]) and (Vg[~inside] == 0x11).all()
+    if S is not None:
+        Sg = S.cpu().numpy()
+        assert np.array_equal(Sg[inside], So[inside]) and (Sg[~inside] == 0x22).all()
+    assert (bufV[:ov] == 0xAB).all() and (bufV[ov + n:] == 0xAB).all()
