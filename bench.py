@@ -529,46 +529,54 @@ def main():
 
     host_submit = []
 
-    def step(times=None):
+    def step(phases=False):
+        """One step.  With phases, events bracket ingest / finalize / segment and the
+        ingest streams are joined before the finalize event (so the ingest phase ends
+        with its last launch); without, the calls run as a user would make them."""
         vol.reset()
-        if times is not None:
+        if phases:
             ev[0].record()
         th = time.perf_counter()
         for fptr, _, pptr, n in chunks:
             st = L.usv_ingest_frames(vol.h, pid, fptr, rp, fp, pptr, n, None)
             if st != 0:
                 raise RuntimeError("ingest failed: %d" % st)
-        if overlap:
+        if overlap and phases:
             L.usv_join(vol.h)
         host_submit.append(time.perf_counter() - th)
-        if times is not None:
+        if phases:
             ev[1].record()
         L.usv_finalize(vol.h, None, Vp, Sp)
-        if times is not None:
+        if phases:
             ev[2].record()
         L.usv_segment_project(vol.h, C.byref(prm), Vp, Sp, *outs)
-        if times is not None:
+        if phases:
             ev[3].record()
-            times.append(ev)
+
+    def phase_steps(n):
+        ph = np.zeros(3)
+        for _ in range(n):
+            step(phases=True)
+            ev[3].synchronize()   # this step's events are read before the next step re-records them
+            ph += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+        torch.cuda.synchronize()
+        return ph / n
 
     for _ in range(max(args.warmup, 0 if args.profile_pass else 1)):
         step()
     torch.cuda.synchronize()
     steps = 1 if args.profile_pass else args.steps
-    phase = np.zeros(3)
     t0 = time.perf_counter()
     for _ in range(steps):
-        tl = []
-        step(tl)
-        ev[3].synchronize()   # this step's events are read before the next step re-records them
-        phase += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = vol.status()
     if st != 0:
         raise RuntimeError("volume status %d after the timed steps" % st)
     ms_step = (t1 - t0) * 1e3 / steps
-    phase /= steps
+    # per-phase times from extra steps with events (not part of the timed region)
+    phase = np.zeros(3) if args.profile_pass else phase_steps(3)
     value = F / (ms_step / 1e3)
     print("[bench] %.3f ms/step  ingest %.3f  finalize %.3f  segment %.3f ms  tile %s  host submit %.3f ms/step" %
           (ms_step, phase[0], phase[1], phase[2], tile, 1e3 * float(np.median(host_submit))), file=sys.stderr,
@@ -589,14 +597,7 @@ def main():
     if overlap:
         overlap = False
         vol.set_ingest_overlap(False)
-        serial = 0.0
-        for _ in range(3):
-            tl = []
-            step(tl)
-            ev[3].synchronize()
-            serial += ev[0].elapsed_time(ev[1])
-        torch.cuda.synchronize()
-        per_launch_ms = serial / 3 / n_kernel
+        per_launch_ms = phase_steps(3)[0] / n_kernel
     else:
         per_launch_ms = overlapped_launch_ms
     per_chunk = q.get(timeout=600)

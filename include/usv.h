@@ -180,7 +180,9 @@ usv_status usv_ingest_frames(usv_volume *vol, int32_t probe_id, const uint8_t *f
  * another kind on this volume (finalize, segment_project, sync, reset, export / import,
  * autotune, graph calls, batched ingest) or at usv_join.  Until then the frames of the
  * burst must stay unchanged and the accumulators must not be read; results are
- * identical to the serial order.  Turning overlap off joins. */
+ * identical to the serial order.  Turning overlap off joins.  usv_finalize enqueues its
+ * zero fill of the outputs outside the live box (it reads no accumulator) before it
+ * joins, so that fill may run beside the burst's last launches. */
 usv_status usv_set_ingest_overlap(usv_volume *vol, int32_t enable);
 /* make the volume's stream wait for any overlapped ingest launches (enqueue only) */
 usv_status usv_join(usv_volume *vol);

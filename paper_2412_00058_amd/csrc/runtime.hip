@@ -802,10 +802,6 @@ usv_status usv_ingest_frames_cut(usv_volume *v, int32_t probe_id, const uint8_t 
 
 usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, uint8_t *state) {
   if (!v || !vol_u8) return fail(v, USV_E_ARG, "null output");
-  {
-    usv_status js = join_side(v);
-    if (js != USV_OK) return js;
-  }
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   FinalizeArgs a{};
   a.sum = v->sum;
@@ -820,10 +816,10 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
   for (int k = 0; k < 3; ++k) {
     if (region) {
       if (region->lo[0] >= region->hi[0] || region->lo[1] >= region->hi[1] || region->lo[2] >= region->hi[2])
-        return USV_OK;   // empty region: nothing can change
+        return join_side(v);   // empty region: nothing can change
       a.lo[k] = std::max(0, region->lo[k] - 1);
       a.hi[k] = std::min(dims[k], region->hi[k] + 1);
-      if (a.lo[k] >= a.hi[k]) return USV_OK;
+      if (a.lo[k] >= a.hi[k]) return join_side(v);
     } else {
       a.lo[k] = 0;
       a.hi[k] = dims[k];
@@ -840,10 +836,15 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
     }
   }
   a.zchunk = 16;   // measured on the whole-spine grid: 16 planes 0.266 ms, 32 planes 0.279 ms, 64 planes 0.302 ms
-  // outputs outside the live box are 0 / EMPTY: written by a plain fill; the stencil
-  // kernel runs over the output box clipped to the live box only
+  // Outputs outside the live box are 0 / EMPTY: written by a plain fill; the stencil
+  // kernel runs over the output box clipped to the live box only.  The fill reads no
+  // accumulator and the live box already covers every ingest call made so far, so it is
+  // enqueued before the ingest streams are joined: with overlapped ingest it runs beside
+  // the last launches of the burst instead of after them.
   usv_status st = check_hip(v, launch_fill_outside(vol_u8, state, v->nx, v->ny, a.lo, a.hi, a.live_lo, a.live_hi,
                                                    v->stream), "finalize fill");
+  if (st != USV_OK) return st;
+  st = join_side(v);
   if (st != USV_OK) return st;
   for (int k = 0; k < 3; ++k) {
     a.lo[k] = std::max(a.lo[k], a.live_lo[k]);
