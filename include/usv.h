@@ -130,7 +130,12 @@ usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *s
  * id.  Width/height 1..32767, pixel sizes > 0.  Up to 16 probes per volume. */
 usv_status usv_add_probe(usv_volume *vol, const usv_probe_desc *probe, int32_t *probe_id);
 
-/* Zero the accumulators (start a new sweep). */
+/* Zero the accumulators (start a new sweep).  With overlapped ingest on, a reset whose
+ * only volume calls since the last usv_finalize are usv_segment_project calls zeroes
+ * the accumulators on a library stream after that finalize's last read of them, beside
+ * whatever is enqueued on the volume's stream after the finalize (the projection); the
+ * next ingest burst and every call of another kind wait for the zeroing.  A caller that
+ * reads the accumulators itself after a finalize calls usv_join before resetting. */
 usv_status usv_reset(usv_volume *vol);
 
 /* Wait for the volume's stream and report the sticky status (USV_OK,

@@ -87,7 +87,16 @@ struct usv_volume {
   hipEvent_t side_ev[2] = {nullptr, nullptr};
   hipEvent_t main_ev = nullptr;
   int next_side = 0;
-  bool side_pending = false;
+  bool side_pending = false;   // the side streams hold work `stream` has not waited for
+  bool burst = false;          // the side streams have waited for `stream` since the last join
+  // Reset beside the projection (overlap on): finalize records acc_ev on `stream` after
+  // its last read of the accumulators; a reset that follows with nothing touching the
+  // accumulators in between zeroes them on side stream 0 after acc_ev, so calls that do
+  // not touch them (segment_project) run beside the zeroing.  zero_ev marks its end for
+  // side stream 1.
+  hipEvent_t acc_ev = nullptr, zero_ev = nullptr;
+  bool acc_quiet = false;      // nothing has touched the accumulators since acc_ev
+  bool zero_pending = false;   // side stream 1 has not yet waited for zero_ev
 };
 
 struct usv_graph {
@@ -139,7 +148,8 @@ usv_status check_hip(usv_volume *v, hipError_t e, const char *what) {
 
 // The volume stream waits for every ingest launch issued on the side streams since the
 // burst began (one event per side stream, recorded here).
-usv_status join_side(usv_volume *v) {
+usv_status join_side(usv_volume *v, bool touches_acc = true) {
+  if (touches_acc) v->acc_quiet = false;
   if (!v->side_pending) return USV_OK;
   for (int k = 0; k < 2; ++k) {
     usv_status st = check_hip(v, hipEventRecord(v->side_ev[k], v->side[k]), "join ingest streams");
@@ -147,6 +157,8 @@ usv_status join_side(usv_volume *v) {
     if (st != USV_OK) return st;
   }
   v->side_pending = false;
+  v->burst = false;
+  v->zero_pending = false;
   return USV_OK;
 }
 
@@ -155,11 +167,15 @@ usv_status join_side(usv_volume *v) {
 // enqueued on the volume stream so far; later launches of the burst add no host calls.
 hipStream_t ingest_stream(usv_volume *v) {
   if (!v->overlap) return v->stream;
-  if (!v->side_pending) {
+  if (!v->burst) {
     if (hipEventRecord(v->main_ev, v->stream) != hipSuccess ||
         hipStreamWaitEvent(v->side[0], v->main_ev, 0) != hipSuccess ||
         hipStreamWaitEvent(v->side[1], v->main_ev, 0) != hipSuccess)
       return nullptr;
+    // a zeroing queued on side stream 0 by a reset precedes every launch of the burst
+    if (v->zero_pending && hipStreamWaitEvent(v->side[1], v->zero_ev, 0) != hipSuccess) return nullptr;
+    v->zero_pending = false;
+    v->burst = true;
     v->side_pending = true;
   }
   return v->side[v->next_side];
@@ -477,6 +493,7 @@ usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *pose
 usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
                          int64_t frame_pitch, const std::vector<float> &maps, const std::vector<int32_t> &fidx,
                          bool safe = false, const std::vector<uint32_t> *rows = nullptr) {
+  v->acc_quiet = false;
   const int nk = (int)fidx.size();
   IngestLaunchRows r{};
   IngestLaunch &a = r.a;
@@ -553,7 +570,17 @@ usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *s
 
 usv_status usv_reset(usv_volume *v) {
   if (!v) return USV_E_ARG;
-  {
+  // beside: the accumulators were last touched by a finalize (acc_ev) and nothing that
+  // touches them has been enqueued since; the zeroing then runs on side stream 0 and
+  // work enqueued meanwhile that leaves them alone runs beside it
+  const bool beside = v->overlap && v->acc_quiet && !v->side_pending && v->acc_ev && v->zero_ev;
+  hipStream_t zs = v->stream;
+  if (beside) {
+    v->acc_quiet = false;
+    usv_status ws = check_hip(v, hipStreamWaitEvent(v->side[0], v->acc_ev, 0), "reset beside");
+    if (ws != USV_OK) return ws;
+    zs = v->side[0];
+  } else {
     usv_status js = join_side(v);
     if (js != USV_OK) return js;
   }
@@ -564,15 +591,21 @@ usv_status usv_reset(usv_volume *v) {
   if (t.lo[0] == 0 && t.lo[1] == 0 && t.lo[2] == 0 && t.hi[0] == full.hi[0] && t.hi[1] == full.hi[1] &&
       t.hi[2] == full.hi[2]) {
     const int64_t words = (int64_t)(usv_accumulator_bytes_of(v) / 4);
-    st = check_hip(v, launch_zero_u32((uint32_t *)v->acc, words, v->stream), "zero accumulators");
+    st = check_hip(v, launch_zero_u32((uint32_t *)v->acc, words, zs), "zero accumulators");
   } else if (!box_empty(t)) {
-    st = check_hip(v, launch_zero_box(v->sum, (uint16_t *)v->cnt32, v->nx, v->ny, t.lo, t.hi, v->stream),
+    st = check_hip(v, launch_zero_box(v->sum, (uint16_t *)v->cnt32, v->nx, v->ny, t.lo, t.hi, zs),
                    "zero accumulators");
+  }
+  if (st == USV_OK) st = check_hip(v, launch_zero_u32(v->d_err, (int64_t)(kStatusBytes / 4), zs), "zero status");
+  if (st == USV_OK && beside) {
+    st = check_hip(v, hipEventRecord(v->zero_ev, v->side[0]), "reset beside");
+    v->zero_pending = true;
+    v->side_pending = true;   // the next call of another kind joins
   }
   if (st != USV_OK) return st;
   v->touched = empty_box();
   v->count_dirty = false;
-  return check_hip(v, launch_zero_u32(v->d_err, (int64_t)(kStatusBytes / 4), v->stream), "zero status");
+  return USV_OK;
 }
 
 }  // extern "C"
@@ -707,6 +740,8 @@ usv_status usv_destroy_volume(usv_volume *v) {
     if (v->side_ev[k]) (void)hipEventDestroy(v->side_ev[k]);
   }
   if (v->main_ev) (void)hipEventDestroy(v->main_ev);
+  if (v->acc_ev) (void)hipEventDestroy(v->acc_ev);
+  if (v->zero_ev) (void)hipEventDestroy(v->zero_ev);
   for (ProbeState &p : v->probes) {
     if (p.d_spans) (void)hipFree(p.d_spans);
     if (p.d_mask) (void)hipFree(p.d_mask);
@@ -738,7 +773,9 @@ usv_status usv_set_ingest_overlap(usv_volume *v, int32_t enable) {
           hipEventCreateWithFlags(&v->side_ev[k], hipEventDisableTiming) != hipSuccess)
         return check_hip(v, hipErrorUnknown, "ingest streams");
     }
-    if (hipEventCreateWithFlags(&v->main_ev, hipEventDisableTiming) != hipSuccess)
+    if (hipEventCreateWithFlags(&v->main_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&v->acc_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&v->zero_ev, hipEventDisableTiming) != hipSuccess)
       return check_hip(v, hipErrorUnknown, "ingest streams");
   }
   v->overlap = true;
@@ -846,19 +883,30 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
   if (st != USV_OK) return st;
   st = join_side(v);
   if (st != USV_OK) return st;
+  bool stencil = true;
   for (int k = 0; k < 3; ++k) {
     a.lo[k] = std::max(a.lo[k], a.live_lo[k]);
     a.hi[k] = std::min(a.hi[k], a.live_hi[k]);
-    if (a.lo[k] >= a.hi[k]) return USV_OK;
+    stencil = stencil && a.lo[k] < a.hi[k];
   }
-  return check_hip(v, launch_finalize(a, v->stream), "finalize launch");
+  if (stencil) {
+    st = check_hip(v, launch_finalize(a, v->stream), "finalize launch");
+    if (st != USV_OK) return st;
+  }
+  // the accumulators are not touched again until the next call of another kind
+  if (v->acc_ev) {
+    st = check_hip(v, hipEventRecord(v->acc_ev, v->stream), "finalize event");
+    if (st != USV_OK) return st;
+    v->acc_quiet = true;
+  }
+  return USV_OK;
 }
 
 usv_status usv_segment_project(usv_volume *v, const usv_seg_params *pr, const uint8_t *vol_u8, const uint8_t *state,
                                int16_t *depth, float *mean, float *max) {
   if (!v || !pr || !vol_u8 || !state || !depth || !mean || !max) return fail(v, USV_E_ARG, "null argument");
   {
-    usv_status js = join_side(v);
+    usv_status js = join_side(v, false);   // reads no accumulator
     if (js != USV_OK) return js;
   }
   if (pr->mode < 0 || pr->mode > 2 || pr->n_half < 1 || pr->n_half > 4) return fail(v, USV_E_ARG, "bad mode / n_half");
@@ -1028,6 +1076,7 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
   usv_volume *owner = vols[0];
   for (int32_t i = 0; i < n_sweeps; ++i) {
     usv_volume *v = vols[i];
+    if (v) v->acc_quiet = false;
     if (!v || !v->side_pending) continue;
     if (join_side(v) != USV_OK) return USV_E_DEVICE;   // records the side events
     if (v != owner)

@@ -393,3 +393,82 @@ def test_finalize_outputs_at_any_alignment(offsets):
         Sg = S.cpu().numpy()
         assert np.array_equal(Sg[inside], So[inside]) and (Sg[~inside] == 0x22).all()
     assert (bufV[:ov] == 0xAB).all() and (bufV[ov + n:] == 0xAB).all()
+
+
+def test_reset_beside_projection():
+    """With overlap on, a reset that follows finalize (and segment_project) zeroes the
+    accumulators on a library stream beside the projection.  Three sweeps in the
+    benchmark's call order with no host synchronisation in between, each checked against
+    the oracle afterwards; then a reset followed by finalize, by export, by a second reset,
+    and by a batched call (as owner and as a non-owner volume) all see zeroed accumulators."""
+    from paper_2412_00058_amd import SEG_ALG2, ingest_batched, seg_params
+    say("case: reset beside the projection")
+    d = synth.cfg1()
+    g, p = d["grid"], d["probe"]
+    nx, ny, nz = g.dims
+    vol = gpu_volume(g)
+    pid = add_probe(vol, p)
+    vol.set_ingest_overlap(True)
+    fr = to_dev(d["frames"])
+    sk = dict(y_lo=1, k=6, tau_I=128, tau_G=30, r=2, fallback_y=20, half=(2, 5))
+    prm = seg_params(mode=SEG_ALG2, **sk)
+    sweeps = [(0, 40), (10, 64), (30, 50)]
+    outs = []
+    for a, b in sweeps:
+        vol.reset()
+        for k in range(a, b, 8):
+            vol.ingest(pid, fr[k:min(k + 8, b)], d["poses"][k:min(k + 8, b)])
+        V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+        S = torch.empty_like(V)
+        vol.finalize(out=(V, S))
+        outs.append((V, S) + tuple(vol.segment_project(prm, V, S)))
+    vol.sync()
+    for (a, b), (V, S, dep, mean, mx) in zip(sweeps, outs):
+        acc = oracle.Accum(g)
+        acc.ingest(d["frames"][a:b], d["poses"][a:b], p)
+        Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+        assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So), (a, b)
+        do, mo, xo = oracle.segment(g, Vo, So, oracle.seg_params(mode=oracle.ALG2, **sk))
+        assert np.array_equal(dep.cpu().numpy(), do)
+        assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32))
+    # reset beside, then finalize: all zero / EMPTY
+    vol.reset()
+    V2, S2 = vol.finalize()
+    vol.sync()
+    assert not V2.any() and not S2.any()
+    # finalize, reset beside, export
+    vol.ingest(pid, fr[:16], d["poses"][:16])
+    vol.finalize(out=(V2, S2))
+    vol.reset()
+    snap = vol.export_accumulators()
+    vol.sync()
+    assert not snap.any()
+    # finalize, reset beside, reset again, ingest
+    vol.ingest(pid, fr[:16], d["poses"][:16])
+    vol.finalize(out=(V2, S2))
+    vol.reset()
+    vol.reset()
+    vol.ingest(pid, fr[20:44], d["poses"][20:44])
+    vol.sync()
+    acc = oracle.Accum(g)
+    acc.ingest(d["frames"][20:44], d["poses"][20:44], p)
+    assert_accum_equal(vol, acc, "reset twice")
+    # reset beside, then batched calls: the volume as owner, then as a non-owner
+    vol2 = gpu_volume(g)
+    pid2 = add_probe(vol2, p)
+    for order in (0, 1):
+        vol.finalize(out=(V2, S2))
+        vol.reset()
+        vol2.reset()
+        jobs = [(vol, pid, fr[:24], d["poses"][:24]), (vol2, pid2, fr[24:48], d["poses"][24:48])]
+        ingest_batched(jobs if order == 0 else jobs[::-1])
+        vol.sync()
+        vol2.sync()
+        acc = oracle.Accum(g)
+        acc.ingest(d["frames"][:24], d["poses"][:24], p)
+        assert_accum_equal(vol, acc, "batched after reset beside, order %d" % order)
+        acc2 = oracle.Accum(g)
+        acc2.ingest(d["frames"][24:48], d["poses"][24:48], p)
+        assert_accum_equal(vol2, acc2, "batched partner, order %d" % order)
+    vol.close()
+    vol2.close()
