@@ -4,6 +4,8 @@
 // 16-byte stores (and loads) per lane where the buffers allow it, so a wave moves 1 KiB
 // per instruction; unaligned heads and tails go word by word (byte by byte for the
 // finalize outputs).
+#include <algorithm>
+
 #include "usv_internal.h"
 
 namespace usv {
@@ -62,6 +64,22 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t d, uint32_t m
   uint32_t q = __umulhi(n, m);
   if (n - q * d >= d) ++q;
   return q;
+}
+
+// Bytes [start, end) of V (blockIdx.y = 0) or S (blockIdx.y = 1) set to zero: 16-byte
+// stores from the first 16-byte boundary of each array, the head and tail byte by byte.
+__global__ __launch_bounds__(256) void zero_span_kernel(uint8_t *V, uint8_t *S, int64_t start, int64_t end) {
+  uint8_t *p = blockIdx.y ? S : V;
+  const uintptr_t pb = (uintptr_t)p;
+  int64_t h = (int64_t)(((pb + (uintptr_t)start + 15) & ~(uintptr_t)15) - pb);
+  if (h > end) h = end;
+  int64_t t16 = (int64_t)(((pb + (uintptr_t)end) & ~(uintptr_t)15) - pb);
+  if (t16 < h) t16 = h;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+  if (t < h - start) p[start + t] = 0;
+  const int64_t n16 = (t16 - h) >> 4;
+  for (int64_t i = t; i < n16; i += stride) *reinterpret_cast<uint4 *>(p + h + 16 * i) = make_uint4(0u, 0u, 0u, 0u);
+  if (t < end - t16) p[t16 + t] = 0;
 }
 
 // V = 0 (blockIdx.y = 0) or state = 0 (blockIdx.y = 1) over the output box minus the live
@@ -145,6 +163,17 @@ hipError_t launch_fill_outside(uint8_t *V, uint8_t *S, int nx, int ny, const int
   }
   if (!live)
     for (int k = 0; k < 3; ++k) a.l_lo[k] = a.l_hi[k] = 0;   // no live row
+  if (o_lo[0] == 0 && o_hi[0] == nx && o_lo[1] == 0 && o_hi[1] == ny) {
+    // whole planes: one contiguous span, zeroed in full (live part included: the stencil
+    // rewrites it afterwards on the same stream).  A plain stream of 16-byte stores runs
+    // at about twice the byte rate of a fill that leaves the live box out (measured on
+    // the whole-spine grid: 215 MB in 33 us against 153 MB in 50 us).
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t start = plane * o_lo[2], end = plane * o_hi[2];
+    const int64_t blocks = std::min<int64_t>(8192, ((end - start) / 16 + 255) / 256 + 1);
+    hipLaunchKernelGGL(zero_span_kernel, dim3((unsigned)blocks, S ? 2 : 1), dim3(256), 0, s, V, S, start, end);
+    return hipGetLastError();
+  }
   a.cpr = (uint32_t)((ex + 15) / 16 + 1);   // chunks a row of ex bytes can touch
   // rows * cpr <= 2 * voxels < 2^32 for grids of fewer than 2^31 voxels
   const uint64_t total = (uint64_t)ey * (uint64_t)ez * a.cpr;

@@ -873,7 +873,8 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
     }
   }
   a.zchunk = 16;   // measured on the whole-spine grid: 16 planes 0.266 ms, 32 planes 0.279 ms, 64 planes 0.302 ms
-  // Outputs outside the live box are 0 / EMPTY: written by a plain fill; the stencil
+  // Outputs outside the live box are 0 / EMPTY: written by a plain fill (for an output
+  // box of whole planes, the whole span: the stencil rewrites the live part); the stencil
   // kernel runs over the output box clipped to the live box only.  The fill reads no
   // accumulator and the live box already covers every ingest call made so far, so it is
   // enqueued before the ingest streams are joined: with overlapped ingest it runs beside
