@@ -1,26 +1,40 @@
 // Normalise + PNN hole fill for gfx950 (Sec. II.C: the second PNN stage fills voxels no
 // pixel reached from their measured neighbours).
 //
-// A block owns a 64 (x) by 16 (y) column of output voxels and marches along z over a
-// chunk of planes.  Lane x of wave w owns rows 4w .. 4w + 3 of the column.  Each step
-// normalises one (66 x 18) plane with a one-voxel halo into LDS words
-// w = measured ? (V | 1 << 16) : 0, and every lane forms the in-plane 3x3 sums of w for
-// its four voxels (a 3-wide column sum over six rows, reused by the four outputs); the
-// 3x3x3 sum is the sum of three consecutive in-plane sums kept in registers.  The sum of
-// w over the 26 neighbours carries sum(V) in its low 16 bits (<= 26 * 255) and the
-// measured count above them.  Raw sums and counts of the next two planes are loaded
-// into registers ahead of use, so each lane keeps three planes of loads in flight;
-// LDS planes are double buffered, one barrier per plane.
+// A block owns a 256 (x) by 6 (y) tile of output voxels and marches along z over a chunk
+// of planes; thread t owns column t of the tile, rows 0 .. 5.  Each step loads one plane
+// of the tile with its one-voxel halo (8 rows of 258 voxels) in row-contiguous 16-byte
+// pieces -- four sums and four counts per load, so a wave reads 1 KiB of one row per
+// instruction (a 64-wide tile read row by row reaches about half the bandwidth on the
+// whole-spine grid) -- normalises it into LDS words w = measured ? (V | 1 << 16) : 0,
+// and every thread forms the in-plane 3x3 sums of w for its six voxels (3-wide sums
+// over eight rows, reused by the six outputs); the 3x3x3 sum is the sum of three
+// consecutive in-plane sums kept in registers.  The sum of w over the 26 neighbours
+// carries sum(V) in its low 16 bits (<= 26 * 255) and the measured count above them.
+// Raw words of the next planes are loaded into registers kDepth planes ahead; LDS planes
+// are triple buffered (a step reads the centre words of plane z while others may
+// already store plane z + 1), one barrier per plane.
+#include <climits>
+
 #include "usv_internal.h"
 
 namespace usv {
 
 namespace {
 
-constexpr int TX = 64, TY = 16, RPW = 4, PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
-constexpr int kHalo = 2 * PY + 2 * TX;   // halo words of a plane: two columns, two rows
-constexpr int kDepth = 3;                // planes of raw loads in flight per lane
-static_assert(kHalo <= 256, "one halo word per thread");
+constexpr int TX = 256, TY = 6, PY = TY + 2;
+// LDS row: halo column x0 - 1 at index 3, tile columns at 4 .. 259 (16-byte aligned
+// pieces), halo column x0 + 256 at 260
+constexpr int PX = 264, PLANE = PX * PY;
+constexpr int kPieces = PY * (TX / 4);          // 4-voxel pieces of a plane: 512
+constexpr int kPPT = kPieces / 256;             // pieces per thread: 2
+constexpr int kEdge = 2 * PY;                   // halo columns: 16 voxels, threads 0 .. 15
+constexpr int kEdgeT0 = 0;
+constexpr int kDepth = 2;                       // planes of raw loads in flight per thread
+// word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format); with it the
+// hardware returns 0 for loads and drops stores at offsets >= num_records
+constexpr int kRsrcWord3 = 0x00020000;
+static_assert(kPieces % 256 == 0 && kEdge <= 256, "whole pieces per thread; one edge voxel per thread");
 
 // floor(num / den) for num < 2^26, 0 < den < 2^18 and a quotient below 2^9: the FP32
 // estimate num * rcp(den) has a relative error below 2^-21, so it is within one of the
@@ -33,194 +47,257 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t den) {
   return q;
 }
 
-__device__ __forceinline__ uint32_t normalise(uint32_t s, uint32_t c) {
-  if (c == 0u) return 0u;
-  if (s > 255u * c) return 255u | (1u << 16);   // mean >= 255.5 before capping
-  uint32_t q = udiv_small(2u * s + c, 2u * c);
-  return (q > 255u ? 255u : q) | (1u << 16);
+// round-half-up(s / c) = floor(s / c + 1/2) for 1 <= c <= 2048 and s <= 255 c, in FP32:
+// s is exact (< 2^19), rcp is within 1 ulp, so fl(s rcp(c)) is within 4.6e-5 of s / c
+// and adding 0.5001 (rounding error < 1.6e-5 below 256.5) lands within [+3.9e-5,
+// +1.7e-4] of s / c + 1/2, whose fractional part is a multiple of 1 / (2c) >= 2.4e-4
+// below 1: the truncation is the floor.
+__device__ __forceinline__ uint32_t round_mean_small(uint32_t s, uint32_t c) {
+  return (uint32_t)((float)s * __builtin_amdgcn_rcpf((float)c) + 0.5001f);
 }
 
-// Raw accumulator words of one plane for this lane: its four own voxels and at most one
-// halo voxel (threads 0 .. kHalo - 1).
+// LDS word of raw (s, c): 0 if c = 0, else round-half-up(s / c) | 1 << 16, capped at
+// 255 (s > 255 c only in imported data).  Selects instead of branches, except for the
+// rare counts above 2048, which take the integer division.
+__device__ __forceinline__ uint32_t normalise(uint32_t s, uint32_t c) {
+  uint32_t q = round_mean_small(s, c);
+  if (c > 2048u) q = udiv_small(2u * s + c, 2u * c);
+  q = s > 255u * c ? 255u : q;   // also covers garbage from c = 0 or a huge s
+  return c ? (q | (1u << 16)) : 0u;
+}
+
+// Raw accumulator words of one plane for this thread: up to kPPT pieces of four voxels
+// (sums; counts packed two per word) and at most one halo-column voxel.
 struct Raw {
-  uint32_t s[RPW], c[RPW];
-  uint32_t hs, hc;
+  uint32_t s[kPPT][4];
+  uint32_t c[kPPT][2];
+  uint32_t es, ec;
 };
 
+// kVec: nx % 4 == 0 and 16-byte aligned sums, 8-byte aligned counts, so a piece is one
+// 16-byte and one 8-byte load; otherwise four 4-byte and four 2-byte loads.
+template <bool kVec>
 __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
-  __shared__ uint32_t plane[2][PLANE];
+  __shared__ __align__(16) uint32_t plane[3][PLANE];
   const int tid = threadIdx.x;
-  const int tx = tid & (TX - 1), wv = tid >> 6;
   // XCD-aware block order: the hardware deals blocks to the 8 XCDs in turn, so block L
   // runs on XCD L % 8.  Each XCD gets a contiguous range of (y, z) bands and runs all x
   // blocks of a band back to back, so the cache lines that neighbouring blocks share
-  // (row ends, halo rows) are fetched into one L2 instead of two.
+  // (halo rows and columns) are fetched into one L2 instead of two.
   const int L = blockIdx.x, xcd = L & 7, j = L >> 3;
   const int band = xcd * a.bands_per_xcd + j / a.gx;
   if (band >= a.gy * a.gz) return;   // padding block
   const int bx = j - (j / a.gx) * a.gx, by = band % a.gy, bz = band / a.gy;
-  const int x0 = a.lo[0] + bx * TX, y0 = a.lo[1] + by * TY;
+  const int x0 = a.xbase + bx * TX, y0 = a.lo[1] + by * TY;
   const int zs = a.lo[2] + bz * a.zchunk;
   const int ze = min(zs + a.zchunk, a.hi[2]);
   const int64_t nxy = (int64_t)a.nx * a.ny;
-  const int x = x0 + tx;
-  const bool xin = x < a.nx;
-  // a block whose outputs all lie outside the live box (every accumulator there and in
-  // its halo is zero, so every output is 0 / EMPTY) writes zeros without reading
-  if (x0 >= a.live_hi[0] || x0 + TX <= a.live_lo[0] || y0 >= a.live_hi[1] || y0 + TY <= a.live_lo[1] ||
-      zs >= a.live_hi[2] || ze <= a.live_lo[2]) {
-    if (!xin || x >= a.hi[0]) return;
-    for (int z = zs; z < ze; ++z) {
-#pragma unroll
-      for (int k = 0; k < RPW; ++k) {
-        const int y = y0 + wv * RPW + k;
-        if (y >= a.hi[1]) continue;
-        const int64_t i = nxy * z + (int64_t)a.nx * y + x;
-        a.V[i] = 0;
-        if (a.state) a.state[i] = 0;
-      }
-    }
-    return;
-  }
-  // Only voxels that an output reads are loaded: x in [lo - 1, hi], y likewise, planes
-  // zs - 1 .. ze (the last block of a row or band and the look-ahead past ze would
-  // otherwise fetch columns, rows and planes no output uses); the rest count as 0.
-  // per-lane 32-bit offsets inside a plane (grids hold < 2^31 voxels); plane bases are uniform
-  uint32_t off[RPW];
-  uint32_t own = 0u;   // bit k: voxel k of this lane is loaded
-#pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int y = y0 + wv * RPW + k;
-    off[k] = (uint32_t)x + (uint32_t)a.nx * (uint32_t)y;
-    if (xin && x <= a.hi[0] && y < a.ny && y <= a.hi[1]) own |= 1u << k;
-  }
-  // this lane's halo voxel (plane coordinates): left / right columns, then top / bottom rows
-  int hpx = -1, hpy = -1;
-  if (tid < 2 * PY) {
-    hpx = tid < PY ? 0 : PX - 1;
-    hpy = tid < PY ? tid : tid - PY;
-  } else if (tid < kHalo) {
-    const int e = tid - 2 * PY;
-    hpx = 1 + (e & (TX - 1));
-    hpy = e < TX ? 0 : PY - 1;
-  }
-  const int hx = x0 - 1 + hpx, hy = y0 - 1 + hpy;
-  const bool hin = hpx >= 0 && hx >= 0 && hx < a.nx && hx <= a.hi[0] && hy >= 0 && hy < a.ny && hy <= a.hi[1];
-  const uint32_t hoff = hin ? (uint32_t)hx + (uint32_t)a.nx * (uint32_t)hy : 0u;
 
-  // loads are unconditional (out-of-grid lanes read voxel 0 of the plane) and masked
+  // Only voxels that an output reads are loaded: x in [lo - 1, hi], y likewise, planes
+  // zs - 1 .. ze; the rest count as 0.  Per piece: its plane offset (32-bit: grids hold
+  // < 2^31 voxels), a 4-bit mask of the voxels loaded, its LDS word index.
+  uint32_t poff[kPPT], pmask[kPPT], plds[kPPT];
+#pragma unroll
+  for (int i = 0; i < kPPT; ++i) {
+    const int pc = tid + 256 * i;
+    const int rr = pc / (TX / 4), jj = pc - rr * (TX / 4);
+    const int y = y0 - 1 + rr, x = x0 + 4 * jj;
+    uint32_t m = 0u;
+    if (pc < kPieces && y >= 0 && y < a.ny && y <= a.hi[1])
+      for (int e = 0; e < 4; ++e)
+        if (x + e >= 0 && x + e < a.nx && x + e <= a.hi[0]) m |= 1u << e;
+    pmask[i] = m;
+    poff[i] = m ? (uint32_t)(x + a.nx * y) : 0u;
+    plds[i] = (uint32_t)(rr * PX + 4 + 4 * jj);
+  }
+  // halo-column voxel of threads kEdgeT0 .. kEdgeT0 + kEdge - 1
+  bool ein = false;
+  uint32_t eoff = 0u, elds = 0u;
+  const bool edge = tid >= kEdgeT0 && tid < kEdgeT0 + kEdge;
+  if (edge) {
+    const int e = tid - kEdgeT0, side = e / PY, rr = e - side * PY;
+    const int x = side ? x0 + TX : x0 - 1, y = y0 - 1 + rr;
+    ein = x >= 0 && x < a.nx && x <= a.hi[0] && y >= 0 && y < a.ny && y <= a.hi[1];
+    eoff = ein ? (uint32_t)(x + a.nx * y) : 0u;
+    elds = (uint32_t)(rr * PX + (side ? 4 + TX : 3));
+  }
+
+  // loads are unconditional (pieces not loaded read voxel 0 of the plane) and masked
   // afterwards: no branches around them
   auto load = [&](int z, Raw &r) {
     const bool zin = z >= 0 && z < a.nz && z <= ze;
-    const uint32_t m = zin ? own : 0u;
-    const uint32_t hm = (zin && hin) ? ~0u : 0u;
     const char *ps = reinterpret_cast<const char *>(a.sum + (zin ? nxy * z : 0));
     const char *pc = reinterpret_cast<const char *>(a.cnt + (zin ? nxy * z : 0));
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) {
-      const uint32_t mk = 0u - ((m >> k) & 1u);
-      r.s[k] = *reinterpret_cast<const uint32_t *>(ps + (size_t)((off[k] << 2) & mk)) & mk;
-      r.c[k] = *reinterpret_cast<const uint16_t *>(pc + (size_t)((off[k] << 1) & mk)) & mk;
+    for (int i = 0; i < kPPT; ++i) {
+      const uint32_t m = zin ? pmask[i] : 0u;
+      const uint32_t o = m ? poff[i] : 0u;
+      if (kVec) {
+        const uint4 sv = *reinterpret_cast<const uint4 *>(ps + (size_t)o * 4u);
+        const uint2 cv = *reinterpret_cast<const uint2 *>(pc + (size_t)o * 2u);
+        r.s[i][0] = sv.x & (0u - (m & 1u));
+        r.s[i][1] = sv.y & (0u - ((m >> 1) & 1u));
+        r.s[i][2] = sv.z & (0u - ((m >> 2) & 1u));
+        r.s[i][3] = sv.w & (0u - ((m >> 3) & 1u));
+        r.c[i][0] = cv.x & ((0xFFFFu & (0u - (m & 1u))) | (0xFFFF0000u & (0u - ((m >> 1) & 1u))));
+        r.c[i][1] = cv.y & ((0xFFFFu & (0u - ((m >> 2) & 1u))) | (0xFFFF0000u & (0u - ((m >> 3) & 1u))));
+      } else {
+        uint32_t cs[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t me = 0u - ((m >> e) & 1u);
+          const uint32_t oe = (o + (uint32_t)e) & me;
+          r.s[i][e] = *reinterpret_cast<const uint32_t *>(ps + (size_t)oe * 4u) & me;
+          cs[e] = *reinterpret_cast<const uint16_t *>(pc + (size_t)oe * 2u) & me;
+        }
+        r.c[i][0] = cs[0] | (cs[1] << 16);
+        r.c[i][1] = cs[2] | (cs[3] << 16);
+      }
     }
-    r.hs = *reinterpret_cast<const uint32_t *>(ps + (size_t)((hoff << 2) & hm)) & hm;
-    r.hc = *reinterpret_cast<const uint16_t *>(pc + (size_t)((hoff << 1) & hm)) & hm;
+    const uint32_t em = (zin && ein) ? ~0u : 0u;
+    r.es = *reinterpret_cast<const uint32_t *>(ps + (size_t)(eoff & em) * 4u) & em;
+    r.ec = *reinterpret_cast<const uint16_t *>(pc + (size_t)(eoff & em) * 2u) & em;
   };
   auto store = [&](int slot, const Raw &r) {
     uint32_t *p = plane[slot];
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) p[(1 + wv * RPW + k) * PX + 1 + tx] = normalise(r.s[k], r.c[k]);
-    if (hpx >= 0) p[hpy * PX + hpx] = normalise(r.hs, r.hc);
-  };
-  // in-plane 3x3 sums of this lane's four voxels, and their centre words
-  auto psum = [&](int slot, uint32_t P[RPW], uint32_t C[RPW]) {
-    const uint32_t *p = plane[slot] + (wv * RPW) * PX + tx;
-    uint32_t col[RPW + 2];
-#pragma unroll
-    for (int r = 0; r < RPW + 2; ++r) {
-      const uint32_t a0 = p[r * PX], a1 = p[r * PX + 1], a2 = p[r * PX + 2];
-      col[r] = a0 + a1 + a2;
-      if (r >= 1 && r <= RPW) C[r - 1] = a1;
+    for (int i = 0; i < kPPT; ++i) {
+      if (tid + 256 * i >= kPieces) break;
+      *reinterpret_cast<uint4 *>(p + plds[i]) =
+          make_uint4(normalise(r.s[i][0], r.c[i][0] & 0xFFFFu), normalise(r.s[i][1], r.c[i][0] >> 16),
+                     normalise(r.s[i][2], r.c[i][1] & 0xFFFFu), normalise(r.s[i][3], r.c[i][1] >> 16));
     }
+    if (edge) p[elds] = normalise(r.es, r.ec);
+  };
+  // in-plane 3x3 sums of this thread's six voxels
+  auto psum = [&](int slot, uint32_t *P) {
+    const uint32_t *p = plane[slot] + 3 + tid;
+    uint32_t col[PY];
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) P[k] = col[k] + col[k + 1] + col[k + 2];
+    for (int r = 0; r < PY; ++r) col[r] = p[r * PX] + p[r * PX + 1] + p[r * PX + 2];
+#pragma unroll
+    for (int k = 0; k < TY; ++k) P[k] = col[k] + col[k + 1] + col[k + 2];
   };
 
   Raw q[kDepth];
-  // planes zs - 1 and zs are normalised first; loads run kDepth planes ahead
+  // in-plane sums of planes z - 1, z, z + 1 (moved down one plane per step)
+  uint32_t Pm[TY], P0[TY], Pp[TY];
+  // planes zs - 1 and zs are normalised first (LDS buffers 0 and 1); loads run kDepth
+  // planes ahead; plane z + 1 goes to buffer (z - zs + 2) mod 3
 #pragma unroll
   for (int d = 0; d < kDepth; ++d) load(zs - 1 + d, q[d]);
-  uint32_t Pm[RPW], P0[RPW], Pp[RPW], Cm[RPW], C0[RPW], Cp[RPW];
-  store((zs - 1) & 1, q[0]);
+  store(0, q[0]);
   load(zs - 1 + kDepth, q[0]);
   __syncthreads();
-  psum((zs - 1) & 1, Pm, Cm);
-  store(zs & 1, q[1]);
+  psum(0, Pm);
+  store(1, q[1]);
   load(zs + kDepth, q[1]);
   __syncthreads();
-  psum(zs & 1, P0, C0);
+  psum(1, P0);
   const uint32_t fmin = (uint32_t)(a.fill_min < 1 ? 1 : a.fill_min);
+  const int x = x0 + tid;
+  const bool xout = x >= a.lo[0] && x < a.hi[0];
+  const uint32_t xoff = (uint32_t)x + (uint32_t)a.nx * (uint32_t)y0;   // plane offset of row 0
+  // Outputs go through buffer resources: a store at an offset past num_records is
+  // dropped by the hardware's range check, so lanes outside the output box store at
+  // offset nrec and, with no state array, the state resource has zero records.  Every
+  // step then issues the same stores with no branch around them, which lets the
+  // compiler keep the loads of later planes in flight across steps.
+  const uint32_t nrec = (uint32_t)(nxy * a.nz);   // < 2^31
+  const __amdgpu_buffer_rsrc_t rV = __builtin_amdgcn_make_buffer_rsrc(a.V, (short)0, (int)nrec, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rS = __builtin_amdgcn_make_buffer_rsrc(a.state ? a.state : a.V, (short)0,
+                                                                      a.state ? (int)nrec : 0, kRsrcWord3);
+  int bz_cur = 1;   // LDS buffer of plane z
   // one plane: r holds the raw words of plane z + 1 and is refilled with plane z + 1 + kDepth
   auto step = [&](int z, Raw &r) {
-    store((z + 1) & 1, r);
+    const int bn = bz_cur == 2 ? 0 : bz_cur + 1;
+    store(bn, r);
     load(z + 1 + kDepth, r);
     __syncthreads();
-    psum((z + 1) & 1, Pp, Cp);
-    if (xin && x < a.hi[0]) {
-      uint8_t *pV = a.V + nxy * z;
-      uint8_t *pS = a.state ? a.state + nxy * z : nullptr;
+    psum(bn, Pp);
+    const uint32_t *cz = plane[bz_cur] + PX + 4 + tid;   // centre words of plane z, row 0
+    const uint32_t zoff = (uint32_t)nxy * (uint32_t)z + xoff;
 #pragma unroll
-      for (int k = 0; k < RPW; ++k) {
-        const int y = y0 + wv * RPW + k;
-        if (y >= a.hi[1]) continue;
-        const uint32_t i = off[k];
-        uint32_t V, st;
-        if (C0[k] >> 16) {
-          V = C0[k] & 0xFFu;
-          st = 1u;
-        } else {
-          const uint32_t nb = Pm[k] + P0[k] + Pp[k];   // centre is 0 (not measured)
-          const uint32_t n = nb >> 16, sv = nb & 0xFFFFu;
-          if (n >= fmin) {
-            V = udiv_small(2u * sv + n, 2u * n);
-            st = 2u;
-          } else {
-            V = 0u;
-            st = 0u;
-          }
-        }
-        pV[i] = (uint8_t)V;
-        if (pS) pS[i] = (uint8_t)st;
-      }
+    for (int k = 0; k < TY; ++k) {
+      const uint32_t i = (xout && y0 + k < a.hi[1]) ? zoff + (uint32_t)a.nx * (uint32_t)k : nrec;
+      // measured: its mean; else the fill from the 26 neighbours (the centre word is 0)
+      // if at least fill_min of them are measured, else 0 / EMPTY; selects, no branches
+      const uint32_t c0 = cz[k * PX];
+      const uint32_t nb = Pm[k] + P0[k] + Pp[k];
+      const uint32_t n = nb >> 16, sv = nb & 0xFFFFu;
+      const bool meas = (c0 >> 16) != 0u, fill = n >= fmin;
+      const uint32_t vf = round_mean_small(sv, n);   // n <= 26, sv <= 255 n (garbage if n = 0)
+      const uint32_t V = meas ? (c0 & 0xFFu) : (fill ? vf : 0u);
+      const uint32_t st = meas ? 1u : (fill ? 2u : 0u);
+      __builtin_amdgcn_raw_buffer_store_b8((uint8_t)V, rV, (int)i, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b8((uint8_t)st, rS, (int)i, 0, 0);
     }
 #pragma unroll
-    for (int k = 0; k < RPW; ++k) {
+    for (int k = 0; k < TY; ++k) {
       Pm[k] = P0[k];
       P0[k] = Pp[k];
-      C0[k] = Cp[k];
     }
+    bz_cur = bn;
   };
-  // the register sets rotate q[2], q[0], q[1] (static indices: no scratch)
-  for (int z = zs; z < ze; z += kDepth) {
-    step(z, q[2]);
+  // the raw register sets alternate q[0], q[1] (static indices: no scratch)
+  static_assert(kDepth == 2, "the loop below alternates two raw register sets");
+  for (int z = zs; z < ze; z += 2) {
+    step(z, q[0]);
     if (z + 1 >= ze) break;
-    step(z + 1, q[0]);
-    if (z + 2 >= ze) break;
-    step(z + 2, q[1]);
+    step(z + 1, q[1]);
   }
 }
 
 }  // namespace
 
+// Blocks of finalize_kernel<kVec> resident on the whole device at once (cached per device).
+template <bool kVec>
+int finalize_slots() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finalize_kernel<kVec>, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+        cus < 1)
+      return 1024;
+    cache[dev] = per_cu * cus;
+  }
+  return cache[dev];
+}
+
 hipError_t launch_finalize(const FinalizeArgs &args, hipStream_t s) {
   const int ex = args.hi[0] - args.lo[0], ey = args.hi[1] - args.lo[1], ez = args.hi[2] - args.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
   FinalizeArgs a = args;
-  a.gx = (ex + TX - 1) / TX;
+  const bool vec = a.nx % 4 == 0 && (((uintptr_t)a.sum) & 15u) == 0 && (((uintptr_t)a.cnt) & 7u) == 0;
+  a.xbase = vec ? (a.lo[0] & ~3) : a.lo[0];   // pieces start on multiples of 4 voxels
+  a.gx = (a.hi[0] - a.xbase + TX - 1) / TX;
   a.gy = (ey + TY - 1) / TY;
+  // Planes per block: a block takes zchunk + 2 plane steps, and the blocks run in rounds
+  // of `slots` (those resident at once), so the time goes as
+  // ceil(blocks / slots) * (zchunk + 2); take the zchunk in [4, 64] that minimises it
+  // (the smaller one on ties): on the whole-spine grid's live box, a single round.
+  const int64_t slots = vec ? finalize_slots<true>() : finalize_slots<false>();
+  int best_zc = 16;
+  int64_t best_cost = INT64_MAX;
+  for (int zc = 4; zc <= 64; ++zc) {
+    const int64_t blocks = (int64_t)a.gx * a.gy * ((ez + zc - 1) / zc);
+    const int64_t cost = ((blocks + slots - 1) / slots) * (zc + 2);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best_zc = zc;
+    }
+  }
+  a.zchunk = best_zc;
   a.gz = (ez + a.zchunk - 1) / a.zchunk;
   a.bands_per_xcd = (a.gy * a.gz + 7) / 8;
   const int64_t blocks = (int64_t)8 * a.bands_per_xcd * a.gx;
-  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (vec)
+    hipLaunchKernelGGL(finalize_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(finalize_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -111,7 +111,8 @@ struct FinalizeArgs {
   int32_t fill_min;
   int32_t lo[3], hi[3];  // output box [lo, hi) (already dilated and clipped)
   int32_t live_lo[3], live_hi[3];   // outside this box every accumulator is zero
-  int32_t zchunk;
+  int32_t zchunk;                      // planes per block (set by launch_finalize)
+  int32_t xbase;                       // x of the first block's first column (set by launch_finalize)
   int32_t gx, gy, gz, bands_per_xcd;   // block grid (set by launch_finalize)
 };
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
