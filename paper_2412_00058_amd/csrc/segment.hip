@@ -254,29 +254,43 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
   const int y0 = wave_min(ya), y1 = wave_max(yz);
   const int64_t nxy = (int64_t)a.nx * a.ny;
   const int64_t base = (int64_t)(active ? z : 0) * nxy + (active ? x : 0);
-  for (int yb = y0; yb <= y1; yb += kUnroll) {
-    int vv[kUnroll], ss[kUnroll];
+  // batches of kUnroll rows, double buffered: the next batch's loads are issued before
+  // the current one is summed.  Loads are unconditional (rows clamped into the grid) and
+  // masked afterwards, so the number in flight is fixed.
+  const uint8_t *pV = a.V + base, *pS = a.state + base;
+  auto load_batch = [&](int yb, uint32_t *vv, uint32_t *ss) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int y = yb + u;
-      const bool in = y >= ya && y <= yz;
-      vv[u] = in ? a.V[base + (int64_t)y * a.nx] : 0;
-      ss[u] = in ? a.state[base + (int64_t)y * a.nx] : 0;
+      const int y = min(yb + u, a.ny - 1);
+      vv[u] = pV[(int64_t)y * a.nx];
+      ss[u] = pS[(int64_t)y * a.nx];
     }
+  };
+  auto sum_batch = [&](int yb, const uint32_t *vv, const uint32_t *ss) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int y = yb + u;
-      if (ss[u] == 0) continue;   // empty or outside this lane's slab
+      if (y < ya || y > yz || ss[u] == 0) continue;   // outside this lane's slab, or empty
       const int ady = y > d ? y - d : d - y;
+      const int v = (int)vv[u];
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         if (h < a.n_half && ady <= a.half[h]) {
-          S[h] += vv[u];
+          S[h] += v;
           C[h] += 1;
-          Mx[h] = max(Mx[h], vv[u]);
+          Mx[h] = max(Mx[h], v);
         }
       }
     }
+  };
+  uint32_t va[kUnroll], sa[kUnroll], vb[kUnroll], sb[kUnroll];
+  if (y0 <= y1) load_batch(y0, va, sa);
+  for (int yb = y0; yb <= y1; yb += 2 * kUnroll) {
+    if (yb + kUnroll <= y1) load_batch(yb + kUnroll, vb, sb);
+    sum_batch(yb, va, sa);
+    if (yb + kUnroll > y1) break;
+    if (yb + 2 * kUnroll <= y1) load_batch(yb + 2 * kUnroll, va, sa);
+    sum_batch(yb + kUnroll, vb, sb);
   }
   if (!active) return;
 #pragma unroll
