@@ -122,7 +122,8 @@ enum { USV_EMPTY = 0, USV_MEASURED = 1, USV_FILLED = 2 };
 size_t usv_accumulator_bytes(const usv_grid_desc *grid);
 
 /* Create a volume over caller-owned device memory accum_dev (usv_accumulator_bytes,
- * 4-byte aligned), zeroing it on `stream`.  dims must be >= 1 with nx*ny*nz < 2^31;
+ * 8-byte aligned: the ingest adds the sums of two neighbouring voxels with one 64-bit
+ * atomic; USV_E_ARG otherwise), zeroing it on `stream`.  dims must be >= 1 with nx*ny*nz < 2^31;
  * voxel_mm > 0 and finite.  *out receives the handle. */
 usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *stream, usv_volume **out);
 

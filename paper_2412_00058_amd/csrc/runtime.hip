@@ -533,7 +533,8 @@ size_t usv_accumulator_bytes(const usv_grid_desc *grid) {
 }
 
 usv_status usv_create_volume(const usv_grid_desc *grid, void *accum_dev, void *stream, usv_volume **out) {
-  if (!out || !grid_ok(grid) || !accum_dev || (((uintptr_t)accum_dev) & 3u)) return USV_E_ARG;
+  // 8-byte aligned: sums of voxel pairs are added with 64-bit atomics
+  if (!out || !grid_ok(grid) || !accum_dev || (((uintptr_t)accum_dev) & 7u)) return USV_E_ARG;
   *out = nullptr;
   usv_volume *v = new (std::nothrow) usv_volume();
   if (!v) return USV_E_OOM;

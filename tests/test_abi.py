@@ -46,6 +46,17 @@ def test_accumulator_bytes_and_grid_validation():
     assert L.usv_accumulator_bytes(C.byref(neg)) == 0
 
 
+def test_create_volume_rejects_misaligned_accumulators():
+    """The ingest adds voxel-pair sums with 64-bit atomics, so the accumulator block must
+    be 8-byte aligned; the check comes before any device work (none is issued here)."""
+    L = _lib.lib()
+    g = U.grid_desc((8, 8, 8))
+    h = C.c_void_p()
+    for addr in (0x1004, 0x1002, 0x100C):
+        assert L.usv_create_volume(C.byref(g), C.c_void_p(addr), None, C.byref(h)) == _lib.USV_E_ARG
+    assert L.usv_create_volume(C.byref(g), None, None, C.byref(h)) == _lib.USV_E_ARG
+
+
 def test_null_handles_are_rejected():
     L = _lib.lib()
     assert L.usv_sync(None) == _lib.USV_E_ARG
