@@ -14,6 +14,7 @@
 // Raw words of the next planes are loaded into registers kDepth planes ahead; LDS planes
 // are triple buffered (a step reads the centre words of plane z while others may
 // already store plane z + 1), one barrier per plane.
+#include <atomic>
 #include <climits>
 
 #include "usv_internal.h"
@@ -250,21 +251,24 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
 
 }  // namespace
 
-// Blocks of finalize_kernel<kVec> resident on the whole device at once (cached per device).
+// Blocks of finalize_kernel<kVec> resident on the whole device at once (cached per
+// device; host threads may race to fill an entry, all with the same value).
 template <bool kVec>
 int finalize_slots() {
-  static int cache[64] = {};
+  static std::atomic<int> cache[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (cache[dev] == 0) {
+  int slots = cache[dev].load(std::memory_order_relaxed);
+  if (slots == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finalize_kernel<kVec>, 256, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
         cus < 1)
       return 1024;
-    cache[dev] = per_cu * cus;
+    slots = per_cu * cus;
+    cache[dev].store(slots, std::memory_order_relaxed);
   }
-  return cache[dev];
+  return slots;
 }
 
 hipError_t launch_finalize(const FinalizeArgs &args, hipStream_t s) {
