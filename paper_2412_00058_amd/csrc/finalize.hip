@@ -52,9 +52,11 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t den) {
 // s is exact (< 2^19), rcp is within 1 ulp, so fl(s rcp(c)) is within 4.6e-5 of s / c
 // and adding 0.5001 (rounding error < 1.6e-5 below 256.5) lands within [+3.9e-5,
 // +1.7e-4] of s / c + 1/2, whose fractional part is a multiple of 1 / (2c) >= 2.4e-4
-// below 1: the truncation is the floor.
+// below 1: the truncation is the floor.  Outside that range (c = 0, s > 255 c, c > 2048)
+// the result is bounded and unused: the callers select another value.
 __device__ __forceinline__ uint32_t round_mean_small(uint32_t s, uint32_t c) {
-  return (uint32_t)((float)s * __builtin_amdgcn_rcpf((float)c) + 0.5001f);
+  const float q = (float)s * __builtin_amdgcn_rcpf((float)(c ? c : 1u)) + 0.5001f;
+  return (uint32_t)fminf(q, 65535.0f);
 }
 
 // LDS word of raw (s, c): 0 if c = 0, else round-half-up(s / c) | 1 << 16, capped at
