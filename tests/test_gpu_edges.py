@@ -472,3 +472,51 @@ def test_reset_beside_projection():
         assert_accum_equal(vol2, acc2, "batched partner, order %d" % order)
     vol.close()
     vol2.close()
+
+
+def test_finalize_extreme_counts_and_sums():
+    """Normalise over the whole range of the accumulators: counts up to 65535 (above
+    2048 the exact integer division is taken), sums up to 2^32 - 1 (above 255 x count the
+    mean is capped at 255), against the oracle on an imported block; and the dense-pixel
+    sweep (thousands of pixels per voxel) finalized from its own ingest."""
+    say("case: finalize extremes")
+    g = synth.Grid((40, 12, 9), (0.0, 0.0, 0.0), 0.5)
+    vol = gpu_volume(g)
+    rng = np.random.default_rng(17)
+    n = g.nvox
+    c = np.zeros(n, np.uint16)
+    s = np.zeros(n, np.uint32)
+    m = rng.random(n) < 0.5
+    k = int(m.sum())
+    cc = np.concatenate([rng.integers(1, 30, k // 3), rng.integers(2000, 2100, k // 3),
+                         rng.integers(30000, 65536, k - 2 * (k // 3))])
+    rng.shuffle(cc)
+    c[m] = cc
+    mean = rng.integers(0, 256, k).astype(np.uint64)
+    half = (cc // 2).astype(np.uint64)
+    sv = np.minimum(cc.astype(np.uint64) * mean + rng.integers(0, 2, k).astype(np.uint64) * half,
+                    np.uint64(0xFFFFFFFF))
+    big = rng.random(k) < 0.05                    # corrupt data: sum above 255 x count
+    sv[big] = np.minimum(cc[big].astype(np.uint64) * 300, np.uint64(0xFFFFFFFF))
+    s[m] = sv.astype(np.uint32)
+    raw = np.zeros(vol.acc.numel() * 4, np.uint8)
+    raw[: 4 * n] = s.view(np.uint8)
+    raw[4 * n: 6 * n] = c.view(np.uint8)
+    vol.import_accumulators(torch.from_numpy(raw.view(np.int32)).cuda())
+    V, S = vol.finalize()
+    vol.sync()
+    Vo, So, _ = oracle.finalize(g, s, c)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    vol.close()
+    case = synth.random_small_case(77, F=4, W=120, H=256, dims=(10, 10, 10), px=0.01, rot_deg=30.0)
+    case["frames"][:2] = 255
+    vol = gpu_volume(case["grid"])
+    pid = add_probe(vol, case["probe"])
+    vol.ingest(pid, to_dev(case["frames"]), case["poses"])
+    V, S = vol.finalize()
+    vol.sync()
+    acc = oracle_accum(case)
+    assert acc.cnt.max() > 2048
+    Vo, So, _ = oracle.finalize(case["grid"], acc.sum, acc.cnt)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    vol.close()
