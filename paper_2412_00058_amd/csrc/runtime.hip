@@ -1154,34 +1154,38 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
     fpos += nf;
   }
   if (items == 0) return USV_OK;
+  if (items > 0x7FFFFFFF) return fail(owner, USV_E_ARG, "batch too large for one launch");
   hipStream_t s = owner->stream;
+  // one stream waits for another through a temporary event
+  auto order = [&](hipStream_t waiter, hipStream_t first) -> usv_status {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(owner, USV_E_OOM, "event");
+    hipError_t r = hipEventRecord(e, first);
+    if (r == hipSuccess) r = hipStreamWaitEvent(waiter, e, 0);
+    (void)hipEventDestroy(e);   // released once the recorded work completes
+    return check_hip(owner, r, "batch stream order");
+  };
   // order after pending work of the other volumes' streams
   for (int32_t i = 1; i < n_sweeps; ++i) {
     if (vols[i]->stream == s) continue;
-    hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(owner, USV_E_OOM, "event");
-    (void)hipEventRecord(e, vols[i]->stream);
-    (void)hipStreamWaitEvent(s, e, 0);
-    (void)hipEventDestroy(e);
+    st = order(s, vols[i]->stream);
+    if (st != USV_OK) return st;
   }
   st = check_hip(owner, hipMemcpyAsync(owner->d_batch, h, bytes, hipMemcpyHostToDevice, s), "batch table upload");
   if (st != USV_OK) return st;
-  (void)hipEventRecord(owner->batch_stage.ev, s);
+  st = check_hip(owner, hipEventRecord(owner->batch_stage.ev, s), "batch table upload");
+  if (st != USV_OK) return st;
   owner->batch_stage.pending = true;
   BatchLaunch a{};
   a.sweeps = (const BatchSweep *)owner->d_batch;
   a.n_sweeps = nsw;
   a.n_items = items;
-  if (items > 0x7FFFFFFF) return fail(owner, USV_E_ARG, "batch too large for one launch");
   st = check_hip(owner, launch_ingest_batched(a, (int)items, s), "batched launch");
   if (st != USV_OK) return st;
   for (int32_t i = 1; i < n_sweeps; ++i) {
     if (vols[i]->stream == s) continue;
-    hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(owner, USV_E_OOM, "event");
-    (void)hipEventRecord(e, s);
-    (void)hipStreamWaitEvent(vols[i]->stream, e, 0);
-    (void)hipEventDestroy(e);
+    st = order(vols[i]->stream, s);
+    if (st != USV_OK) return st;
   }
   return USV_OK;
 }
