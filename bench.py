@@ -446,8 +446,8 @@ def main():
                          dbs[2] if len(dbs) > 2 else None, args.counters_tile)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the library runs on a single GPU; how the path would "
-              "shard over several GPUs is a design (DESIGN.md, section 9), not code", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single GPU, and sharding the "
+              "path over several GPUs is a documented design, not code", file=sys.stderr)
         sys.exit(2)
 
     global _SWEEP
