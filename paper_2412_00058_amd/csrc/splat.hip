@@ -368,28 +368,50 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
   const int64_t we64 = any ? (int64_t)wx * wy * wz : 0;
   const bool staged = any && we64 <= kSplatWin;
+  // this thread's pixel values (rows ty0, ty0 + 8, ...), loaded first so that they arrive
+  // while the window is staged
+  const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
+  const int u = u0 + tx;
+  constexpr int kRowsPT = STH / 8;
+  float vals[kRowsPT];
+#pragma unroll
+  for (int k = 0; k < kRowsPT; ++k) {
+    const int v = v0 + ty0 + 8 * k;
+    vals[k] = (any && u <= u1 && v <= v1) ? I[((int64_t)f * g.H + v) * g.W + u] : 0.0f;
+  }
   if (staged) {
-    // one window row (wx voxels along x) per group of lanes; rows are contiguous in HBM
+    // window entries in groups of kStage per thread: all loads of a group are issued
+    // before its LDS stores (entries past the end re-read the last one and are not
+    // stored), so a block waits for one memory round trip per group, not per entry
     const int we = (int)we64;
     const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
-    for (int e = threadIdx.x; e < we; e += 256) {
-      const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
-      const int ix = e - r1 * wx;
-      const int ez = wy == 1 ? r1 : (int)__umulhi((uint32_t)r1, mag_wy);
-      const int ey = r1 - ez * wy;
-      const int64_t gi = (int64_t)(lo[0] + ix) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
-      gwin[e] = make_float2(GS[gi], GW[gi]);
+    constexpr int kStage = 8;
+    for (int e0 = threadIdx.x; e0 < we; e0 += 256 * kStage) {
+      float2 gv[kStage];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int e = min(e0 + 256 * k, we - 1);
+        const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
+        const int ix = e - r1 * wx;
+        const int ez = wy == 1 ? r1 : (int)__umulhi((uint32_t)r1, mag_wy);
+        const int ey = r1 - ez * wy;
+        const int64_t gi =
+            (int64_t)(lo[0] + ix) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
+        gv[k] = make_float2(GS[gi], GW[gi]);
+      }
+#pragma unroll
+      for (int k = 0; k < kStage; ++k)
+        if (e0 + 256 * k < we) gwin[e0 + 256 * k] = gv[k];
     }
   }
   __syncthreads();
-  const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
-  const int u = u0 + tx;
   float acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int ty = ty0; ty < STH; ty += 8) {
-    const int v = v0 + ty;
+#pragma unroll
+  for (int kr = 0; kr < kRowsPT; ++kr) {
+    const int v = v0 + ty0 + 8 * kr;
     if (!any || u > u1 || v > v1) continue;
     const int64_t pix = ((int64_t)f * g.H + v) * g.W + u;
-    const float val = I[pix];
+    const float val = vals[kr];
     PixW p;
     double pd[3];
     pixel_coord(m, u, v, g, p, pd);
