@@ -406,15 +406,9 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   }
   __syncthreads();
   float acc[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int kr = 0; kr < kRowsPT; ++kr) {
-    const int v = v0 + ty0 + 8 * kr;
-    if (!any || u > u1 || v > v1) continue;
-    const int64_t pix = ((int64_t)f * g.H + v) * g.W + u;
-    const float val = vals[kr];
-    PixW p;
-    double pd[3];
-    pixel_coord(m, u, v, g, p, pd);
+  // dI of one pixel and its terms of the pose gradient, from its 8 corner values
+  // (corners outside the grid contribute nothing)
+  auto accumulate = [&](const PixW &p, const double *pd, float val, const float *gs, const float *gw, int64_t pix) {
     float di = 0.0f, gq[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int dlt = 0; dlt < 8; ++dlt) {
@@ -423,19 +417,8 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
       const float fx = bx ? p.f[0] : 1.0f - p.f[0];
       const float fy = by ? p.f[1] : 1.0f - p.f[1];
       const float fz = bz ? p.f[2] : 1.0f - p.f[2];
-      const int cx = p.i0[0] + bx, cy = p.i0[1] + by, cz = p.i0[2] + bz;
-      float gs, gw;
-      if (staged) {
-        const float2 gg = gwin[(cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2]))];
-        gs = gg.x;
-        gw = gg.y;
-      } else {
-        const int64_t gi = (int64_t)cx + (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
-        gs = GS[gi];
-        gw = GW[gi];
-      }
-      di += fx * fy * fz * gs;
-      const float coef = val * gs + gw;
+      di += fx * fy * fz * gs[dlt];
+      const float coef = val * gs[dlt] + gw[dlt];
       gq[0] += coef * (bx ? 1.0f : -1.0f) * fy * fz;
       gq[1] += coef * (by ? 1.0f : -1.0f) * fx * fz;
       gq[2] += coef * (bz ? 1.0f : -1.0f) * fx * fy;
@@ -448,6 +431,60 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
     acc[3] += ry * gq[2] - rz * gq[1];
     acc[4] += rz * gq[0] - rx * gq[2];
     acc[5] += rx * gq[1] - ry * gq[0];
+  };
+  if (staged) {
+    // two pixels at a time: all 16 corner reads from LDS are issued before either
+    // pixel's terms are formed (reads of corners a pixel does not use go to entry 0)
+#pragma unroll
+    for (int k2 = 0; k2 < kRowsPT; k2 += 2) {
+      PixW p[2];
+      double pd[2][3];
+      float gs[2][8], gw[2][8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int v = v0 + ty0 + 8 * (k2 + h);
+        const bool in = u <= u1 && v <= v1;
+        pixel_coord(m, u, v, g, p[h], pd[h]);
+#pragma unroll
+        for (int dlt = 0; dlt < 8; ++dlt) {
+          const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+          const bool ok = in && (bx ? p[h].ok1[0] : p[h].ok0[0]) && (by ? p[h].ok1[1] : p[h].ok0[1]) &&
+                          (bz ? p[h].ok1[2] : p[h].ok0[2]);
+          const int cx = p[h].i0[0] + bx, cy = p[h].i0[1] + by, cz = p[h].i0[2] + bz;
+          const int idx = ok ? (cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2])) : 0;
+          const float2 t = gwin[idx];
+          gs[h][dlt] = t.x;
+          gw[h][dlt] = t.y;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int v = v0 + ty0 + 8 * (k2 + h);
+        if (u > u1 || v > v1) continue;
+        accumulate(p[h], pd[h], vals[k2 + h], gs[h], gw[h], ((int64_t)f * g.H + v) * g.W + u);
+      }
+    }
+  } else if (any) {
+    // window too large for LDS: corners gathered from the gradient volumes
+    for (int kr = 0; kr < kRowsPT; ++kr) {
+      const int v = v0 + ty0 + 8 * kr;
+      if (u > u1 || v > v1) continue;
+      PixW p;
+      double pd[3];
+      pixel_coord(m, u, v, g, p, pd);
+      float gs[8], gw[8];
+#pragma unroll
+      for (int dlt = 0; dlt < 8; ++dlt) {
+        const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
+        const bool ok = (bx ? p.ok1[0] : p.ok0[0]) && (by ? p.ok1[1] : p.ok0[1]) && (bz ? p.ok1[2] : p.ok0[2]);
+        const int64_t gi = ok ? (int64_t)(p.i0[0] + bx) +
+                                    (int64_t)g.nx * ((int64_t)(p.i0[1] + by) + (int64_t)g.ny * (p.i0[2] + bz))
+                              : 0;
+        gs[dlt] = GS[gi];
+        gw[dlt] = GW[gi];
+      }
+      accumulate(p, pd, vals[kr], gs, gw, ((int64_t)f * g.H + v) * g.W + u);
+    }
   }
   // pixels of a tile outside the grid still get dL/dI = 0
   if (!any && dI) {
