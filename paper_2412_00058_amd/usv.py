@@ -23,6 +23,27 @@ def _vp(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def _need(cond, msg: str):
+    """Argument check of the binding (raised before any device call; the C ABI cannot see
+    tensor sizes, so a short buffer would otherwise be read or written past its end)."""
+    if not cond:
+        raise ValueError(msg)
+
+
+def _check_frames(frames, hw=None):
+    _need(isinstance(frames, torch.Tensor) and frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3,
+          "frames: uint8 device tensor [F, H, W]")
+    _need(frames.stride(2) == 1, "frames: consecutive bytes along a row")
+    if hw is not None:
+        _need(frames.shape[1] >= hw[0] and frames.shape[2] >= hw[1],
+              "frames: %d x %d smaller than the probe image %d x %d" % (frames.shape[1], frames.shape[2], hw[0], hw[1]))
+
+
+def _check_buf(t, dtype, numel: int, what: str):
+    _need(isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_cuda and t.is_contiguous() and t.numel() >= numel,
+          "%s: contiguous %s device tensor of at least %d elements" % (what, dtype, numel))
+
+
 def _stream_ptr() -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -48,7 +69,7 @@ def probe_desc(width, height, pixel_mm, calib=None, mask=None):
     keep = None
     if mask is not None:
         keep = np.ascontiguousarray(mask, dtype=np.uint8)
-        assert keep.shape == (height, width)
+        _need(keep.shape == (height, width), "mask: [height, width] array")
         p.mask_host = keep.ctypes.data
     else:
         p.mask_host = None
@@ -86,10 +107,12 @@ def cut_rows_alg1(width, height, pixel_mm, poses, params: CutParams, calib=None)
 def cut_rows_alg2(frames: torch.Tensor, params: CutParams, scratch=None, rows=None) -> torch.Tensor:
     """Table II Steps 2-4 on a uint8 device stack [F, H, W]: int32 [F, 2] row bands on the
     device, computed on the current stream."""
-    assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3 and frames.stride(2) == 1
+    _check_frames(frames)
     F, H, W = frames.shape
     scratch = torch.empty(F * (W + 1), dtype=torch.int16, device=frames.device) if scratch is None else scratch
     rows = torch.empty((F, 2), dtype=torch.int32, device=frames.device) if rows is None else rows
+    _check_buf(scratch, torch.int16, F * (W + 1), "cut scratch")
+    _check_buf(rows, torch.int32, 2 * F, "cut rows")
     check(lib().usv_cut_rows_alg2(_vp(frames), frames.stride(1), frames.stride(0), F, W, H, C.byref(params),
                                   _vp(scratch), _vp(rows), _stream_ptr()))
     return rows
@@ -98,7 +121,8 @@ def cut_rows_alg2(frames: torch.Tensor, params: CutParams, scratch=None, rows=No
 def extract_slices(V: torch.Tensor, axis: int = 2, first: int = 0, count: Optional[int] = None) -> torch.Tensor:
     """Slices of a uint8 device volume [nz, ny, nx] perpendicular to `axis` (2 = z, the
     spine axis of the sweeps here), on the device: [count, rows, cols]."""
-    assert V.dtype == torch.uint8 and V.is_cuda and V.dim() == 3 and V.is_contiguous()
+    _need(isinstance(V, torch.Tensor) and V.dtype == torch.uint8 and V.is_cuda and V.dim() == 3 and V.is_contiguous(),
+          "slices: contiguous uint8 device volume [nz, ny, nx]")
     nz, ny, nx = V.shape
     n_axis = (nx, ny, nz)[axis]
     count = n_axis - first if count is None else count
@@ -154,6 +178,7 @@ class Volume:
         check(L.usv_create_volume(C.byref(self.desc), _vp(self.acc), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self._keep = []
+        self._probe_hw = {}   # probe id -> (rows, columns) of its images
 
     def close(self):
         if getattr(self, "h", None):
@@ -179,6 +204,7 @@ class Volume:
         p, keep = probe_desc(width, height, pixel_mm, calib, mask)
         pid = C.c_int32()
         check(lib().usv_add_probe(self.h, C.byref(p), C.byref(pid)), self.h)
+        self._probe_hw[pid.value] = (int(height), int(width))
         return pid.value
 
     def tiling(self, probe_id):
@@ -197,11 +223,10 @@ class Volume:
 
     def ingest(self, probe_id, frames: torch.Tensor, poses) -> Box:
         """frames: uint8 device tensor [F, H, W] (row pitch = stride); poses [F, 4, 4] FP64 host."""
-        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3
-        assert frames.stride(2) == 1
+        _check_frames(frames, self._probe_hw.get(probe_id))
         P = _poses(poses)
         n = frames.shape[0]
-        assert P.shape[0] == n
+        _need(P.shape[0] == n, "one pose per frame")
         box = Box()
         check(lib().usv_ingest_frames(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                       P.ctypes.data_as(C.c_void_p), n, C.byref(box)), self.h)
@@ -218,13 +243,12 @@ class Volume:
     def ingest_cut(self, probe_id, frames: torch.Tensor, poses, rows) -> Box:
         """ingest() restricted to each frame's band of rows (int32 [F, 2] first/last row,
         host array or tensor): the cut images Img_C of the tissue segmentation."""
-        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3
-        assert frames.stride(2) == 1
+        _check_frames(frames, self._probe_hw.get(probe_id))
         P = _poses(poses)
         n = frames.shape[0]
         R = rows.cpu().numpy() if isinstance(rows, torch.Tensor) else np.asarray(rows)
         R = np.ascontiguousarray(R, dtype=np.int32).reshape(-1, 2)
-        assert P.shape[0] == n and R.shape[0] == n
+        _need(P.shape[0] == n and R.shape[0] == n, "one pose and one row band per frame")
         box = Box()
         check(lib().usv_ingest_frames_cut(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                           P.ctypes.data_as(C.c_void_p), R.ctypes.data_as(C.c_void_p), n,
@@ -238,17 +262,26 @@ class Volume:
             S = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.acc.device) if with_state else None
         else:
             V, S = out
+            _check_buf(V, torch.uint8, self.nvox, "finalize output V")
+            if S is not None:
+                _check_buf(S, torch.uint8, self.nvox, "finalize output state")
         check(lib().usv_finalize(self.h, C.byref(region) if region is not None else None, _vp(V), _vp(S)), self.h)
         return V, S
 
     def segment_project(self, params: SegParams, V, S, out=None):
         nx, ny, nz = self.dims
+        _check_buf(V, torch.uint8, self.nvox, "segment input V")
+        _check_buf(S, torch.uint8, self.nvox, "segment input state")
+        _need(0 <= params.n_half <= 4, "segment: at most 4 half widths")
         if out is None:
             depth = torch.empty((nz, nx), dtype=torch.int16, device=V.device)
             mean = torch.empty((params.n_half, nz, nx), dtype=torch.float32, device=V.device)
             mx = torch.empty((params.n_half, nz, nx), dtype=torch.float32, device=V.device)
         else:
             depth, mean, mx = out
+            _check_buf(depth, torch.int16, nz * nx, "segment output depth")
+            _check_buf(mean, torch.float32, params.n_half * nz * nx, "segment output mean")
+            _check_buf(mx, torch.float32, params.n_half * nz * nx, "segment output max")
         check(lib().usv_segment_project(self.h, C.byref(params), _vp(V), _vp(S), _vp(depth), _vp(mean), _vp(mx)),
               self.h)
         return depth, mean, mx
@@ -264,10 +297,14 @@ class Volume:
 
     def export_accumulators(self, dst: Optional[torch.Tensor] = None) -> torch.Tensor:
         dst = torch.empty_like(self.acc) if dst is None else dst
+        _need(isinstance(dst, torch.Tensor) and dst.is_cuda and dst.is_contiguous() and
+              dst.numel() * dst.element_size() >= self.acc.numel() * 4, "export: device buffer of the accumulator size")
         check(lib().usv_export_accumulators(self.h, _vp(dst)), self.h)
         return dst
 
     def import_accumulators(self, src: torch.Tensor):
+        _need(isinstance(src, torch.Tensor) and src.is_cuda and src.is_contiguous() and
+              src.numel() * src.element_size() >= self.acc.numel() * 4, "import: device buffer of the accumulator size")
         check(lib().usv_import_accumulators(self.h, _vp(src)), self.h)
 
     def autotune(self, probe_id, frames: torch.Tensor, poses, cache_path: Optional[str] = None):
@@ -429,9 +466,9 @@ class VNN:
         check(lib().usv_vnn_reset(self.h))
 
     def ingest(self, frames: torch.Tensor, poses):
-        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3 and frames.stride(2) == 1
+        _check_frames(frames)
         P = _poses(poses)
-        assert P.shape[0] == frames.shape[0]
+        _need(P.shape[0] == frames.shape[0], "one pose per frame")
         check(lib().usv_vnn_ingest(self.h, _vp(frames), frames.stride(1), frames.stride(0),
                                    P.ctypes.data_as(C.c_void_p), frames.shape[0]))
 
@@ -496,8 +533,10 @@ class SplatContext:
     def dw_ingest(self, acc, frames: torch.Tensor, poses_dev: torch.Tensor):
         """Distance-weighted compounding of uint8 frames [F, H, W] (device) at image->world
         poses (FP64 device [F, 4, 4]) into acc."""
-        assert frames.dtype == torch.uint8 and frames.is_cuda and frames.dim() == 3 and frames.stride(2) == 1
+        _check_frames(frames)
         P = poses_dev.contiguous()
+        _need(P.is_cuda and P.dtype == torch.float64 and P.numel() == 16 * frames.shape[0],
+              "dw poses: FP64 device tensor [F, 4, 4]")
         check(lib().usv_dw_ingest(self.h, _vp(frames), frames.stride(1), frames.stride(0), _vp(P), frames.shape[0],
                                   _vp(acc)))
 

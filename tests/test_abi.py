@@ -151,3 +151,16 @@ def test_slice_and_cut_argument_validation():
     assert L.usv_vnn_ingest(None, None, 0, 0, None, 0) == E
     assert L.usv_dw_ingest(None, None, 0, 0, None, 0, None) == E
     assert L.usv_refine_motion(None, None, None, 0, None, None, None, None, None) == E
+
+
+def test_binding_rejects_bad_tensors_before_any_device_call():
+    """The binding checks tensor kinds and sizes that the C ABI cannot see (host tensors,
+    wrong dtypes, short buffers) and raises ValueError without touching a device."""
+    import torch
+    from paper_2412_00058_amd import cut_params, cut_rows_alg2, extract_slices
+    with pytest.raises(ValueError):
+        cut_rows_alg2(torch.zeros((2, 8, 8), dtype=torch.uint8), cut_params())
+    with pytest.raises(ValueError):
+        extract_slices(torch.zeros((4, 4, 4), dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        U.probe_desc(8, 6, (0.1, 0.1), None, np.ones((5, 8), np.uint8))

@@ -520,3 +520,33 @@ def test_finalize_extreme_counts_and_sums():
     Vo, So, _ = oracle.finalize(case["grid"], acc.sum, acc.cnt)
     assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
     vol.close()
+
+
+def test_binding_checks_tensor_sizes():
+    """Frames smaller than the probe image, outputs shorter than the grid and host tensors
+    are refused by the binding with ValueError (no device work is issued for them); the
+    volume is still usable afterwards."""
+    say("case: binding size checks")
+    d = synth.cfg1()
+    g = d["grid"]
+    nx, ny, nz = g.dims
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    fr = to_dev(d["frames"])
+    with pytest.raises(ValueError):
+        vol.ingest(pid, fr[:4, :-1], d["poses"][:4])              # one row short
+    with pytest.raises(ValueError):
+        vol.ingest(pid, fr[:4].cpu(), d["poses"][:4])             # host frames
+    with pytest.raises(ValueError):
+        vol.ingest(pid, fr[:4], d["poses"][:3])                   # one pose missing
+    V = torch.empty(g.nvox - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        vol.finalize(out=(V, None))
+    with pytest.raises(ValueError):
+        vol.export_accumulators(torch.empty(4, dtype=torch.int32, device="cuda"))
+    vol.ingest(pid, fr[:8], d["poses"][:8])
+    vol.sync()
+    acc = oracle.Accum(g)
+    acc.ingest(d["frames"][:8], d["poses"][:8], d["probe"])
+    assert_accum_equal(vol, acc, "after refused calls")
+    vol.close()
