@@ -179,11 +179,25 @@ def _spine_frame(args):
     return n, A, img
 
 
+def _gpu_runtime_started() -> bool:
+    """True once this process has initialised the GPU through torch (device memory for
+    the HIP path always comes from torch).  A process in that state must not fork: the
+    child would inherit the runtime's threads and handles half-copied."""
+    import sys
+    t = sys.modules.get("torch")
+    try:
+        return bool(t is not None and t.cuda.is_initialized())
+    except Exception:
+        return True
+
+
 def _pool_map(fn, items, workers):
     if workers <= 1 or len(items) < 8:
         return [fn(a) for a in items]
     import multiprocessing as mp
-    ctx = mp.get_context("fork")
+    # fork is cheap and safe before any GPU call; afterwards the workers are spawned
+    # (fresh interpreters that import only numpy and this module)
+    ctx = mp.get_context("spawn" if _gpu_runtime_started() else "fork")
     with ctx.Pool(workers) as pool:
         return pool.map(fn, items, chunksize=max(1, len(items) // (workers * 8)))
 
