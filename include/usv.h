@@ -289,7 +289,8 @@ usv_status usv_vnn_destroy(usv_vnn *ctx);
 
 /* ---------------------------------------------------------------------------------
  * Batched multi-sweep ingest: n_sweeps independent (volume, probe, frames, poses)
- * jobs compounded by one persistent launch on the first volume's stream.  All
+ * jobs compounded by one kernel launch on the first volume's stream, one block per
+ * (sweep, frame, tile) item of every sweep's current tiling (usv_autotune).  All
  * volumes must live on the same device.  Per sweep the result equals
  * usv_ingest_frames on that sweep alone (bit for bit).  dirty_out: n_sweeps boxes or
  * NULL.
@@ -320,6 +321,7 @@ usv_status usv_probe_chunk(const usv_volume *vol, int32_t probe_id, int32_t *fra
  * 120x64, 120x32, 240x16, 240x32, 240x8; anything else is USV_E_UNSUPPORTED.  Results
  * do not depend on the tiling (bit for bit), only the speed does. */
 usv_status usv_probe_set_tiling(usv_volume *vol, int32_t probe_id, int32_t tile_w, int32_t tile_h);
+
 
 /* ---------------------------------------------------------------------------------
  * Real-time single-frame ingest through captured HIP graphs (Sec. II.C / III.B: one

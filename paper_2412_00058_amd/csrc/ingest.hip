@@ -123,7 +123,7 @@ __device__ __forceinline__ uint32_t pixel_phase(const SweepDesc &d, const uint8_
   const uint32_t wbase = (uint32_t)(w.lo0 + w.wx * (w.lo1 + w.wy * w.lo2));
   const uint32_t wx = (uint32_t)w.wx, wy = (uint32_t)w.wy;
   // window byte offset = 4 (iz wx wy + iy wx + ix - wbase)  (mod 2^32)
-  const uint32_t wx4 = 4u * wx, wxy4 = 4u * wx * wy, nb4 = 0u - 4u * wbase;
+  const uint32_t wx4 = 4u * wx, wxy4 = 4u * wx * wy, wxy = wx * wy, nb4 = 0u - 4u * wbase;
   const uint32_t one = 1u << t.cshift;   // one pixel in the count field
   if (kFast) {
 #pragma unroll
@@ -133,7 +133,9 @@ __device__ __forceinline__ uint32_t pixel_phase(const SweepDesc &d, const uint8_
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t ix = (uint32_t)(a0[j] + c.x), iy = (uint32_t)(a1[j] + c.y), iz = (uint32_t)(a2[j] + c.z);
-        const uint32_t boff = __umul24(iy, wx4) + __umul24(iz, wxy4) + ((ix << 2) + nb4);
+        // entry = ix + wx iy + wx wy iz (two 24-bit multiply-adds), byte offset = 4 entry - 4 wbase
+        const uint32_t ent = __umul24(iz, wxy) + (__umul24(iy, wx) + ix);
+        const uint32_t boff = (ent << 2) + nb4;
         atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(win) + boff),
                   one + ((pre[k] >> (8 * j)) & 0xFFu));
       }
@@ -355,9 +357,14 @@ __device__ __forceinline__ void tile_once(const SweepDesc &d, const uint8_t *__r
 template <bool kAligned, bool kDevMaps, bool kRows = false>
 __device__ __forceinline__ void run_block(const SweepDesc &d, const float *__restrict__ Mdev,
                                           const int32_t *__restrict__ fdev, const float (*Marg)[9],
-                                          const int32_t *farg, Smem &sm, const uint32_t *rows = nullptr) {
+                                          const int32_t *farg, Smem &sm, const uint32_t *rows = nullptr,
+                                          int per_xcd = 0, int n_items = 0) {
   const Tiling &t = d.t;
-  const uint32_t it = blockIdx.x;
+  // XCD-aware order (per_xcd > 0): block b runs on XCD b % 8, and each XCD takes a
+  // contiguous range of items, so the tiles of one row (which share the cache lines at
+  // their borders) are read through one L2
+  const uint32_t it = per_xcd > 0 ? (blockIdx.x & 7u) * (uint32_t)per_xcd + (blockIdx.x >> 3) : blockIdx.x;
+  if (per_xcd > 0 && it >= (uint32_t)n_items) return;
   const uint32_t per_frame = (uint32_t)(t.tiles_x * t.tiles_y);
   const int f = (int)udiv_m(it, per_frame, t.pf_magic);
   const int tile = (int)(it - (uint32_t)f * per_frame);
@@ -386,13 +393,15 @@ __device__ __forceinline__ void run_block(const SweepDesc &d, const float *__res
 __global__ __launch_bounds__(kBlock) void ingest_kernel(IngestLaunch a) {
   __shared__ __align__(16) Smem sm;
   const SweepDesc d = a.d;
-  run_block<true, false>(d, nullptr, nullptr, a.M, a.fidx, sm);
+  run_block<true, false>(d, nullptr, nullptr, a.M, a.fidx, sm, nullptr, a.per_xcd,
+                         a.n_frames * d.t.tiles_x * d.t.tiles_y);
 }
 
 __global__ __launch_bounds__(kBlock) void ingest_kernel_bytes(IngestLaunch a) {
   __shared__ __align__(16) Smem sm;
   const SweepDesc d = a.d;
-  run_block<false, false>(d, nullptr, nullptr, a.M, a.fidx, sm);
+  run_block<false, false>(d, nullptr, nullptr, a.M, a.fidx, sm, nullptr, a.per_xcd,
+                          a.n_frames * d.t.tiles_x * d.t.tiles_y);
 }
 
 // With a band of image rows per frame (rows in the argument segment too).
@@ -492,14 +501,16 @@ __global__ __launch_bounds__(256) void count_final_kernel(const unsigned long lo
 
 }  // namespace
 
-hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s) {
+hipError_t launch_ingest(const IngestLaunch &a0, int n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
+  IngestLaunch a = a0;
+  a.per_xcd = (n_items + 7) / 8;
   const bool aligned = (a.d.row_pitch % 4 == 0) && (a.d.frame_pitch % 4 == 0) &&
                        ((((uintptr_t)a.d.frames) & 3u) == 0);
   if (aligned)
-    hipLaunchKernelGGL(ingest_kernel, dim3(n_items), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(ingest_kernel, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(ingest_kernel_bytes, dim3(n_items), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(ingest_kernel_bytes, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -162,6 +162,14 @@ usv_status join_side(usv_volume *v, bool touches_acc = true) {
   return USV_OK;
 }
 
+// Wait until every launch queued by the volume so far has finished (before a table that
+// queued launches read is replaced).
+usv_status quiesce(usv_volume *v) {
+  usv_status st = join_side(v, false);
+  if (st != USV_OK) return st;
+  return check_hip(v, hipStreamSynchronize(v->stream), "wait for queued launches");
+}
+
 // Stream of the next ingest launch: the volume stream, or (overlap) the next side stream.
 // The first launch of a burst (after a join) makes both side streams wait for everything
 // enqueued on the volume stream so far; later launches of the burst add no host calls.
@@ -385,11 +393,10 @@ hipError_t upload_tile_class_for(const ProbeState &p, const Tiling &t, uint8_t *
   return hipMemcpy(dst, cls.data(), cls.size(), hipMemcpyHostToDevice);
 }
 
-hipError_t upload_tile_class(ProbeState &p) {
-  hipError_t e = upload_tile_class_for(p, p.t, p.d_tile_class);
-  if (e != hipSuccess) return e;
-  return upload_tile_class_for(p, p.t_safe, p.d_tile_class_safe);
-}
+// The table of the probe's current tiling.  Retiling replaces it, so callers first wait
+// for every queued launch of the volume (quiesce).  The table of the safe tiling never
+// changes after add_probe: captured graphs keep its address in their kernel arguments.
+hipError_t upload_tile_class(ProbeState &p) { return upload_tile_class_for(p, p.t, p.d_tile_class); }
 
 SweepDesc make_desc(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
                     int64_t frame_pitch, bool safe = false) {
@@ -677,6 +684,7 @@ usv_status usv_add_probe(usv_volume *v, const usv_probe_desc *pd, int32_t *probe
   p.t = default_tiling(p, v->s, false);
   p.t_safe = default_tiling(p, v->s, true);
   usv_status st = check_hip(v, upload_tile_class(p), "tile classes");
+  if (st == USV_OK) st = check_hip(v, upload_tile_class_for(p, p.t_safe, p.d_tile_class_safe), "tile classes");
   if (st != USV_OK) return st;
   v->probes.push_back(std::move(p));
   *probe_id = (int32_t)v->probes.size() - 1;
@@ -973,7 +981,8 @@ usv_status usv_probe_set_tiling(usv_volume *v, int32_t probe_id, int32_t tile_w,
   for (const TileCand &c : kCands) {
     Tiling t = make_tiling(c.lr, c.kr, p.W, p.H);
     if (t.tw == tile_w && t.th == tile_h && tiling_valid(t)) {
-      (void)hipStreamSynchronize(v->stream);   // tile classes in use by queued launches
+      const usv_status qs = quiesce(v);   // tile classes in use by queued launches
+      if (qs != USV_OK) return qs;
       p.t = t;
       return check_hip(v, upload_tile_class(p), "tile classes");
     }
@@ -1220,6 +1229,8 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
         if (!(ss >> chunk >> ms) || chunk < 1 || chunk > kLaunchFrames) chunk = kLaunchFrames;
         Tiling t = make_tiling(lr, kr, p.W, p.H);
         if (!tiling_valid(t)) break;
+        const usv_status qs = quiesce(v);   // tile classes in use by queued launches
+        if (qs != USV_OK) return qs;
         p.t = t;
         p.chunk = chunk;
         return check_hip(v, upload_tile_class(p), "tile classes");

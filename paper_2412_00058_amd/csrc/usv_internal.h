@@ -54,6 +54,7 @@ struct SweepDesc {
 struct IngestLaunch {
   SweepDesc d;
   int32_t n_frames;
+  int32_t per_xcd;                 // items per XCD (block b takes item (b % 8) per_xcd + b / 8)
   int32_t fidx[kLaunchFrames];     // frame index in the caller's buffer
   float M[kLaunchFrames][9];       // per frame: rows r = (du, dv, const)
 };

@@ -503,23 +503,50 @@ class SplatContext:
         self.dims = tuple(int(d) for d in dims)
         self.nvox = self.dims[0] * self.dims[1] * self.dims[2]
         self.W, self.H = int(width), int(height)
+        self.max_frames = int(max_frames)
+
+    # argument checks (the C ABI sees raw pointers only)
+    def _frames_f32(self, I, what="I"):
+        _check_buf(I, torch.float32, 0, what)
+        _need(I.dim() == 3 and I.shape[1] == self.H and I.shape[2] == self.W,
+              "%s: FP32 device tensor [F, %d, %d]" % (what, self.H, self.W))
+        F = int(I.shape[0])
+        _need(F <= self.max_frames, "%s: %d frames, the context holds at most %d" % (what, F, self.max_frames))
+        return F
+
+    @staticmethod
+    def _poses(Tstar, xi, F):
+        _check_buf(Tstar, torch.float64, 16 * F, "Tstar")
+        _need(Tstar.numel() == 16 * F, "Tstar: FP64 device tensor [F, 4, 4]")
+        _check_buf(xi, torch.float64, 6 * F, "xi")
+        _need(xi.numel() == 6 * F, "xi: FP64 device tensor [F, 6]")
+
+    def _vols(self, v, what, n=4):
+        _check_buf(v, torch.float32, n * self.nvox, what)
 
     def forward(self, I, Tstar, xi, vols=None):
-        F = I.shape[0]
+        F = self._frames_f32(I)
+        self._poses(Tstar, xi, F)
         vols = torch.empty((4, self.nvox), dtype=torch.float32, device=I.device) if vols is None else vols
+        self._vols(vols, "vols")
         check(lib().usv_splat_forward(self.h, _vp(I), _vp(Tstar), _vp(xi), F, _vp(vols)))
         return vols
 
     def loss(self, vols, want_grads=True):
+        self._vols(vols, "vols")
         loss = torch.empty(1, dtype=torch.float64, device=vols.device)
-        grads = torch.empty_like(vols) if want_grads else None
+        grads = torch.empty((4, self.nvox), dtype=torch.float32, device=vols.device) if want_grads else None
         check(lib().usv_overlap_loss(self.h, _vp(vols), _vp(loss), _vp(grads)))
         return loss, grads
 
     def backward(self, I, Tstar, xi, grads, dI=None, dxi=None):
-        F = I.shape[0]
+        F = self._frames_f32(I)
+        self._poses(Tstar, xi, F)
+        self._vols(grads, "grads")
         dI = torch.empty_like(I) if dI is None else dI
+        _check_buf(dI, torch.float32, F * self.H * self.W, "dI")
         dxi = torch.empty((F, 6), dtype=torch.float64, device=I.device) if dxi is None else dxi
+        _check_buf(dxi, torch.float64, 6 * F, "dxi")
         check(lib().usv_splat_backward(self.h, _vp(I), _vp(Tstar), _vp(xi), F, _vp(grads), _vp(dI), _vp(dxi)))
         return dI, dxi
 
@@ -527,13 +554,17 @@ class SplatContext:
         """(Re)zeroed distance-weighted accumulator FP32 [2, nvox] (sum w I, sum w)."""
         if acc is None:
             acc = torch.empty((2, self.nvox), dtype=torch.float32, device="cuda")
+        self._vols(acc, "acc", 2)
         check(lib().usv_dw_clear(self.h, _vp(acc)))
         return acc
 
     def dw_ingest(self, acc, frames: torch.Tensor, poses_dev: torch.Tensor):
         """Distance-weighted compounding of uint8 frames [F, H, W] (device) at image->world
         poses (FP64 device [F, 4, 4]) into acc."""
-        _check_frames(frames)
+        _check_frames(frames, (self.H, self.W))
+        _need(frames.shape[0] <= self.max_frames,
+              "frames: %d frames, the context holds at most %d" % (frames.shape[0], self.max_frames))
+        self._vols(acc, "acc", 2)
         P = poses_dev.contiguous()
         _need(P.is_cuda and P.dtype == torch.float64 and P.numel() == 16 * frames.shape[0],
               "dw poses: FP64 device tensor [F, 4, 4]")
@@ -542,6 +573,7 @@ class SplatContext:
 
     def dw_finalize(self, acc, w_min=0.05):
         nx, ny, nz = self.dims
+        self._vols(acc, "acc", 2)
         V = torch.empty((nz, ny, nx), dtype=torch.float32, device=acc.device)
         S = torch.empty((nz, ny, nx), dtype=torch.uint8, device=acc.device)
         check(lib().usv_dw_finalize(self.h, _vp(acc), C.c_float(w_min), _vp(V), _vp(S)))
@@ -552,7 +584,9 @@ class SplatContext:
         """Adam on one rigid motion xi (rho mm, omega rad) applied to the odd frames
         (T_n = Exp(xi) T*_n) that minimises the overlap loss; runs asynchronously on the
         stream.  Returns (xi [6] fp64, loss [iters + 1] fp64)."""
-        F = I.shape[0]
+        F = self._frames_f32(I)
+        _check_buf(Tstar, torch.float64, 16 * F, "Tstar")
+        _need(Tstar.numel() == 16 * F, "Tstar: FP64 device tensor [F, 4, 4]")
         dev = I.device
         xi = torch.zeros(6, dtype=torch.float64, device=dev)
         if xi0 is not None:
@@ -560,6 +594,8 @@ class SplatContext:
         loss = torch.empty(int(iters) + 1, dtype=torch.float64, device=dev)
         vols = torch.empty((4, self.nvox), dtype=torch.float32, device=dev) if vols is None else vols
         grads = torch.empty((4, self.nvox), dtype=torch.float32, device=dev) if grads is None else grads
+        self._vols(vols, "vols")
+        self._vols(grads, "grads")
         prm = RefineParams(int(iters), float(lr_rho), float(lr_omega), float(beta1), float(beta2), float(eps))
         check(lib().usv_refine_motion(self.h, _vp(I), _vp(Tstar), F, C.byref(prm), _vp(xi), _vp(loss), _vp(vols),
                                       _vp(grads)))

@@ -94,6 +94,36 @@ def test_graph_with_convex_mask_equals_oracle():
     assert_accum_equal(vol, oracle_accum(case), "graph masked")
 
 
+def test_graph_survives_retiling_of_its_probe():
+    """A captured graph keeps the address of its probe's tile-class table in its kernel
+    arguments; retiling the probe afterwards (set_tiling, autotune) must leave the graph
+    working: frames launched through it before and after the retiling, plus frames
+    ingested by the retiled plain path, equal the oracle bit for bit."""
+    from paper_2412_00058_amd import Graph
+    say("case: graph, then set_tiling and autotune of a fan-masked probe")
+    case = synth.random_small_case(72, F=16, W=96, H=80, dims=(40, 36, 40), px=0.2, rot_deg=30.0)
+    p = case["probe"]
+    m = synth.convex_mask(p.width, p.height, p.pixel_mm[0], apex_mm=2.0, half_angle_deg=30.0)
+    case["probe"] = synth.Probe(p.width, p.height, p.pixel_mm, mask=m)
+    case["frames"] = case["frames"] * m[None]
+    vol = gpu_volume(case["grid"])
+    pid = add_probe(vol, case["probe"])
+    gr = Graph(vol, pid)
+    fr = case["frames"]
+    for n in range(4):
+        gr.launch(fr[n], case["poses"][n])
+    vol.set_tiling(pid, 32, 32)
+    for n in range(4, 8):
+        gr.launch(fr[n], case["poses"][n])
+    vol.autotune(pid, to_dev(fr[:8]), case["poses"][:8], None)
+    for n in range(8, 12):
+        gr.launch(fr[n], case["poses"][n])
+    vol.ingest(pid, to_dev(fr[12:]), case["poses"][12:])
+    vol.sync()
+    gr.close()
+    assert_accum_equal(vol, oracle_accum(case), "graph after retiling")
+
+
 def test_whole_spine_sweep_full_size_bit_exact():
     """3600 frames of 480 x 640 into the 400 x 240 x 1120 grid, ingested in calls of 64 with
     the autotuned tiling and overlapped launches (the benchmark's configuration);
@@ -550,3 +580,48 @@ def test_binding_checks_tensor_sizes():
     acc.ingest(d["frames"][:8], d["poses"][:8], d["probe"])
     assert_accum_equal(vol, acc, "after refused calls")
     vol.close()
+
+
+def test_splat_binding_checks():
+    """The splat context refuses, with ValueError and before any device call, FP32 poses
+    read as FP64, frames of another size, host tensors, more frames than the context
+    holds and volume/gradient/accumulator buffers shorter than the grid; afterwards a
+    correct call still matches the FP64 oracle."""
+    from paper_2412_00058_amd import SplatContext
+    say("case: splat binding checks")
+    d = synth.small_splat()
+    g, p = d["grid"], d["probe"]
+    F = d["I"].shape[0]
+    ctx = SplatContext(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, F)
+    I = to_dev(d["I"])
+    Ts = to_dev(d["Tstar"])
+    xi = to_dev(d["xi"])
+    nvox = g.nvox
+    bad = [
+        lambda: ctx.forward(I, Ts, xi.float()),                          # FP32 xi
+        lambda: ctx.forward(I, Ts.float(), xi),                          # FP32 poses
+        lambda: ctx.forward(I[:, :-1], Ts, xi),                          # one row short
+        lambda: ctx.forward(I.cpu(), Ts, xi),                            # host frames
+        lambda: ctx.forward(torch.cat([I, I]), torch.cat([Ts, Ts]), torch.cat([xi, xi])),   # > max_frames
+        lambda: ctx.forward(I, Ts[:-1], xi),                             # one pose missing
+        lambda: ctx.forward(I, Ts, xi, torch.empty(4 * nvox - 1, dtype=torch.float32, device="cuda")),
+        lambda: ctx.loss(torch.empty(4 * nvox - 1, dtype=torch.float32, device="cuda")),
+        lambda: ctx.backward(I, Ts, xi, torch.empty(3 * nvox, dtype=torch.float32, device="cuda")),
+        lambda: ctx.backward(I, Ts, xi, torch.empty(4 * nvox, dtype=torch.float32, device="cuda"),
+                             dI=torch.empty(5, dtype=torch.float32, device="cuda")),
+        lambda: ctx.backward(I, Ts, xi, torch.empty(4 * nvox, dtype=torch.float32, device="cuda"),
+                             dxi=torch.empty(6 * F - 1, dtype=torch.float64, device="cuda")),
+        lambda: ctx.dw_clear(torch.empty(2 * nvox - 1, dtype=torch.float32, device="cuda")),
+    ]
+    for k, f in enumerate(bad):
+        with pytest.raises(ValueError):
+            f()
+            say("  accepted bad call", k)
+    vols = ctx.forward(I, Ts, xi)
+    torch.cuda.synchronize()
+    o = oracle.splat_forward(g, d["I"], d["Tstar"], d["xi"], p)
+    v = vols.cpu().numpy().astype(np.float64).reshape(4, -1)
+    for k in range(4):
+        ref = o[k].reshape(-1)
+        assert np.linalg.norm(v[k] - ref) <= 1e-5 * np.linalg.norm(ref)
+    ctx.close()
