@@ -311,8 +311,8 @@ def test_new_entry_points_edge_cases():
     ctx.dw_ingest(acc, fr[:3], to_dev(off))
     torch.cuda.synchronize()
     assert not acc.any()
-    with pytest.raises(UsvError):
-        ctx.dw_ingest(acc, fr[:9], to_dev(d["poses"][:9]))     # more than max_frames
+    with pytest.raises(ValueError):
+        ctx.dw_ingest(acc, fr[:9], to_dev(d["poses"][:9]))     # more than max_frames (binding check)
     # refinement with a single (even) frame: no moving frame, no overlap term, loss 0
     I = torch.rand((1, p.height, p.width), device="cuda")
     xi, L = ctx.refine_motion(I, to_dev(d["poses"][:1]), iters=3)
