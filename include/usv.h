@@ -209,6 +209,24 @@ usv_status usv_finalize(usv_volume *vol, const usv_box *region, uint8_t *vol_u8_
 usv_status usv_segment_project(usv_volume *vol, const usv_seg_params *params, const uint8_t *vol_u8_dev,
                                const uint8_t *state_dev, int16_t *depth_dev, float *mean_dev, float *max_dev);
 
+/* usv_segment_project for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation): no volume handle,
+ * and no hipMalloc, hipFree or allocating call of any kind.  The grid comes as a
+ * descriptor (dims, origin_mm and voxel_mm are used), the inputs and outputs are as for
+ * usv_segment_project, and the work is enqueued on `stream` (a hipStream_t, NULL = the
+ * default stream).  The raw per-column contour depths live in a fixed scratch array of
+ * the library, USV_NOALLOC_MAX_COLUMNS int16 entries (4 MiB) per device, held by each
+ * device the library runs on until the process ends; its device address is looked up on
+ * the first call on a device.  Grids with nx * nz > USV_NOALLOC_MAX_COLUMNS return
+ * USV_E_UNSUPPORTED before any device work; bad arguments return USV_E_ARG; a failed
+ * launch USV_E_DEVICE.  Every call on one device shares that scratch: calls that overlap
+ * on one device (other streams, other threads) race and must be serialised by the
+ * caller. */
+#define USV_NOALLOC_MAX_COLUMNS (1 << 21)
+usv_status usv_segment_project_noalloc(const usv_grid_desc *grid, const usv_seg_params *params,
+                                       const uint8_t *vol_u8_dev, const uint8_t *state_dev, int16_t *depth_dev,
+                                       float *mean_dev, float *max_dev, void *stream);
+
 /* ---------------------------------------------------------------------------------
  * Image-space tissue segmentation (Sec. II.D, Tables I and II): before compounding,
  * each frame is cut to a band of rows around its depth of cut (the cut image Img_C),

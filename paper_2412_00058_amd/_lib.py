@@ -16,7 +16,7 @@ EXPORTS = [
     "usv_accumulator_bytes", "usv_create_volume", "usv_add_probe", "usv_reset", "usv_sync",
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
     "usv_ingest_frames", "usv_ingest_frames_cut", "usv_set_ingest_overlap", "usv_join", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_vnn_create", "usv_vnn_reset", "usv_vnn_ingest",
-    "usv_vnn_finalize", "usv_vnn_destroy", "usv_extract_slices", "usv_finalize", "usv_segment_project", "usv_ingest_batched", "usv_autotune",
+    "usv_vnn_finalize", "usv_vnn_destroy", "usv_extract_slices", "usv_finalize", "usv_segment_project", "usv_segment_project_noalloc", "usv_ingest_batched", "usv_autotune",
     "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
     "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
@@ -107,6 +107,7 @@ def lib():
         "usv_cut_rows_alg2": (I32, [P, I64, I64, I32, I32, I32, C.POINTER(CutParams), P, P, P]),
         "usv_finalize": (I32, [P, C.POINTER(Box), P, P]),
         "usv_segment_project": (I32, [P, C.POINTER(SegParams), P, P, P, P, P]),
+        "usv_segment_project_noalloc": (I32, [C.POINTER(GridDesc), C.POINTER(SegParams), P, P, P, P, P, P]),
         "usv_ingest_batched": (I32, [P, P, P, P, P, P, P, I32, P]),
         "usv_autotune": (I32, [P, I32, P, I64, I64, P, I32, C.c_char_p]),
         "usv_probe_tiling": (I32, [P, I32, C.POINTER(I32), C.POINTER(I32)]),

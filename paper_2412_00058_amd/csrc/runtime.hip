@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -525,6 +526,76 @@ usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *fram
   return USV_OK;
 }
 
+bool seg_params_ok(const usv_seg_params *pr, int32_t ny) {
+  if (pr->mode < 0 || pr->mode > 2 || pr->n_half < 1 || pr->n_half > 4) return false;
+  for (int i = 0; i < pr->n_half; ++i)
+    if (pr->half[i] < 0 || pr->half[i] > 255) return false;
+  if (pr->mode == USV_SEG_ALG2)
+    return !(pr->k < 1 || pr->k > 64 || pr->r < 0 || pr->r > 8 || pr->y_lo < 0 || pr->fallback_y < 0 ||
+             pr->fallback_y >= ny);
+  const double chk[5] = {pr->K, pr->D_mm, pr->L_mm, pr->z1_mm, pr->yref_mm};
+  return finite_all(chk, 5);
+}
+
+SegArgs seg_args(const usv_seg_params *pr, const uint8_t *vol_u8, const uint8_t *state, int16_t *raw, int16_t *depth,
+                 float *mean, float *max, int32_t nx, int32_t ny, int32_t nz, const double origin[3], double s) {
+  SegArgs a{};
+  a.V = vol_u8;
+  a.state = state;
+  a.raw = raw;
+  a.depth = depth;
+  a.mean = mean;
+  a.max = max;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.mode = pr->mode;
+  a.y_lo = pr->y_lo;
+  a.k = pr->k;
+  a.tau_I = pr->tau_I;
+  a.tau_G = pr->tau_G;
+  a.r = pr->r;
+  a.fallback_y = pr->fallback_y;
+  a.n_half = pr->n_half;
+  for (int i = 0; i < 4; ++i) a.half[i] = i < pr->n_half ? pr->half[i] : 0;
+  a.K = pr->K;
+  a.D_mm = pr->D_mm;
+  a.L_mm = pr->L_mm;
+  a.z1_mm = pr->z1_mm;
+  a.yref_mm = pr->yref_mm;
+  a.origin_y = origin[1];
+  a.origin_z = origin[2];
+  a.s = s;
+  a.row_pitch = nx;
+  a.plane_pitch = (int64_t)nx * ny;
+  return a;
+}
+
+// Fixed scratch of usv_segment_project_noalloc: the raw contour depth of every (x, z)
+// column before the median (fully written by the contour pass before the median reads
+// it, so it needs no clearing).  Each device holds its own copy for the life of the
+// process; its device address is taken once per device with hipGetSymbolAddress (the
+// host-side name is not a device address).  Calls on one device share it.
+constexpr int64_t kStaticRawColumns = USV_NOALLOC_MAX_COLUMNS;
+static __device__ __align__(256) int16_t scratch[kStaticRawColumns];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int16_t *g_scratch_ptr[kMaxDevices] = {};
+
+usv_status static_raw_scratch(int16_t **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return USV_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return USV_E_DEVICE;
+    g_scratch_ptr[dev] = (int16_t *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return USV_OK;
+}
+
 size_t usv_accumulator_bytes_of(const usv_volume *v) {
   return (size_t)(4 * v->nvox + 2 * ((v->nvox + 1) & ~(int64_t)1));
 }
@@ -918,48 +989,24 @@ usv_status usv_segment_project(usv_volume *v, const usv_seg_params *pr, const ui
     usv_status js = join_side(v, false);   // reads no accumulator
     if (js != USV_OK) return js;
   }
-  if (pr->mode < 0 || pr->mode > 2 || pr->n_half < 1 || pr->n_half > 4) return fail(v, USV_E_ARG, "bad mode / n_half");
-  for (int i = 0; i < pr->n_half; ++i)
-    if (pr->half[i] < 0 || pr->half[i] > 255) return fail(v, USV_E_ARG, "half width out of range");
-  if (pr->mode == USV_SEG_ALG2) {
-    if (pr->k < 1 || pr->k > 64 || pr->r < 0 || pr->r > 8 || pr->y_lo < 0 || pr->fallback_y < 0 ||
-        pr->fallback_y >= v->ny)
-      return fail(v, USV_E_ARG, "bad ALG2 parameters");
-  } else {
-    const double chk[5] = {pr->K, pr->D_mm, pr->L_mm, pr->z1_mm, pr->yref_mm};
-    if (!finite_all(chk, 5)) return fail(v, USV_E_ARG, "non-finite depth parameters");
-  }
+  if (!seg_params_ok(pr, v->ny)) return fail(v, USV_E_ARG, "bad segmentation parameters");
   if (v->sticky == USV_E_DEVICE) return v->sticky;
-  SegArgs a{};
-  a.V = vol_u8;
-  a.state = state;
-  a.raw = v->d_raw;
-  a.depth = depth;
-  a.mean = mean;
-  a.max = max;
-  a.nx = v->nx;
-  a.ny = v->ny;
-  a.nz = v->nz;
-  a.mode = pr->mode;
-  a.y_lo = pr->y_lo;
-  a.k = pr->k;
-  a.tau_I = pr->tau_I;
-  a.tau_G = pr->tau_G;
-  a.r = pr->r;
-  a.fallback_y = pr->fallback_y;
-  a.n_half = pr->n_half;
-  for (int i = 0; i < 4; ++i) a.half[i] = i < pr->n_half ? pr->half[i] : 0;
-  a.K = pr->K;
-  a.D_mm = pr->D_mm;
-  a.L_mm = pr->L_mm;
-  a.z1_mm = pr->z1_mm;
-  a.yref_mm = pr->yref_mm;
-  a.origin_y = v->origin[1];
-  a.origin_z = v->origin[2];
-  a.s = v->s;
-  a.row_pitch = v->nx;
-  a.plane_pitch = (int64_t)v->nx * v->ny;
+  const SegArgs a = seg_args(pr, vol_u8, state, v->d_raw, depth, mean, max, v->nx, v->ny, v->nz, v->origin, v->s);
   return check_hip(v, launch_segment(a, v->stream), "segment launch");
+}
+
+usv_status usv_segment_project_noalloc(const usv_grid_desc *grid, const usv_seg_params *pr, const uint8_t *vol_u8,
+                                       const uint8_t *state, int16_t *depth, float *mean, float *max,
+                                       void *stream) {
+  if (!grid_ok(grid) || !pr || !vol_u8 || !state || !depth || !mean || !max) return USV_E_ARG;
+  if (!seg_params_ok(pr, grid->dims[1])) return USV_E_ARG;
+  if ((int64_t)grid->dims[0] * grid->dims[2] > kStaticRawColumns) return USV_E_UNSUPPORTED;
+  int16_t *raw = nullptr;
+  const usv_status st = static_raw_scratch(&raw);
+  if (st != USV_OK) return st;
+  const SegArgs a = seg_args(pr, vol_u8, state, raw, depth, mean, max, grid->dims[0], grid->dims[1], grid->dims[2],
+                             grid->origin_mm, grid->voxel_mm);
+  return launch_segment(a, (hipStream_t)stream) == hipSuccess ? USV_OK : USV_E_DEVICE;
 }
 
 usv_status usv_probe_tiling(const usv_volume *v, int32_t probe_id, int32_t *tile_w, int32_t *tile_h) {

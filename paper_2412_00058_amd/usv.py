@@ -491,6 +491,24 @@ class VNN:
             pass
 
 
+def segment_project_noalloc(dims, origin_mm, voxel_mm, params: SegParams, V: torch.Tensor, S: torch.Tensor,
+                            depth: torch.Tensor, mean: torch.Tensor, mx: torch.Tensor):
+    """usv_segment_project_noalloc: bone depth + slab projection of a finalized uint8
+    volume V / state S ([nz][ny][nx]) into caller-provided outputs (depth int16 [nz][nx],
+    mean and max FP32 [n_half][nz][nx]) on the current torch stream, with no device
+    allocation by the library (a fixed scratch of USV_NOALLOC_MAX_COLUMNS columns)."""
+    nx, ny, nz = (int(d) for d in dims)
+    nv = nx * ny * nz
+    _check_buf(V, torch.uint8, nv, "V")
+    _check_buf(S, torch.uint8, nv, "S")
+    _check_buf(depth, torch.int16, nx * nz, "depth")
+    _check_buf(mean, torch.float32, params.n_half * nx * nz, "mean")
+    _check_buf(mx, torch.float32, params.n_half * nx * nz, "max")
+    g = grid_desc(dims, origin_mm, voxel_mm)
+    check(lib().usv_segment_project_noalloc(C.byref(g), C.byref(params), _vp(V), _vp(S), _vp(depth), _vp(mean),
+                                            _vp(mx), _stream_ptr()))
+
+
 class SplatContext:
     """Geometry + scratch of the trilinear splat on the current torch stream."""
 
