@@ -55,6 +55,13 @@ def lib():
         L.orc_splat_backward.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_double, P, P, P, C.c_int, C.c_int,
                                          C.c_int, C.c_double, C.c_double, P, P, P, P, P, P]
         L.orc_splat_backward.restype = None
+        L.orc_mt_ingest_nearest.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, C.c_int64,
+                                            C.c_int64, P, P, C.c_int, C.c_int]
+        L.orc_mt_ingest_nearest.restype = C.c_int64
+        L.orc_mt_finalize.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]
+        L.orc_mt_finalize.restype = C.c_int64
+        L.orc_mt_segment.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_double, P, P, P, P, P, P, C.c_int]
+        L.orc_mt_segment.restype = None
         _lib = L
     return _lib
 
@@ -123,6 +130,18 @@ class Accum:
                                         stamp_p, self.stamp_id, C.byref(nd),
                                         None if rows is None else _p(_c(rows, np.int32).reshape(F, 2)))
         return int(kept), (int(nd.value) if count_distinct else -1)
+
+    def ingest_mt(self, frames, poses, probe, n_threads, calib=None):
+        """ingest() by n_threads threads, each owning a slab of z planes (same bits)."""
+        calib = np.eye(4) if calib is None else calib
+        frames = _c(frames, np.uint8)
+        F, H, W = frames.shape
+        assert W == probe.width and H == probe.height
+        M = _c(fold_all(poses, calib, probe, self.grid).reshape(F, 9), np.float32)
+        mask = None if probe.mask is None else _c(probe.mask, np.uint8)
+        nx, ny, nz = self.grid.dims
+        return int(lib().orc_mt_ingest_nearest(nx, ny, nz, _p(self.sum), _p(self.cnt), C.byref(self.overflow),
+                                               _p(frames), W, H, W, H * W, _p(M), _p(mask), F, int(n_threads)))
 
     @property
     def overflowed(self) -> bool:
@@ -200,6 +219,16 @@ def finalize(grid, sum_, cnt, fill_min=1):
     return V.reshape(nz, ny, nx), st.reshape(nz, ny, nx), int(bad)
 
 
+def finalize_mt(grid, sum_, cnt, n_threads, fill_min=1):
+    """finalize() by n_threads threads (slabs of z planes; same bits)."""
+    nx, ny, nz = grid.dims
+    V = np.empty(grid.nvox, dtype=np.uint8)
+    st = np.empty(grid.nvox, dtype=np.uint8)
+    bad = lib().orc_mt_finalize(nx, ny, nz, _p(_c(sum_, np.uint32)), _p(_c(cnt, np.uint16)), int(fill_min),
+                                _p(V), _p(st), int(n_threads))
+    return V.reshape(nz, ny, nx), st.reshape(nz, ny, nx), int(bad)
+
+
 # --- segmentation + projection ------------------------------------------------------------
 
 ALG2, ALG1, FIXED = 0, 1, 2
@@ -221,6 +250,18 @@ def seg_params(mode=ALG2, y_lo=0, k=6, tau_I=128, tau_G=40, r=2, fallback_y=0, h
         p.half[i] = h
     p.K, p.D_mm, p.L_mm, p.z1_mm, p.yref_mm = K, D_mm, L_mm, z1_mm, yref_mm
     return p
+
+
+def segment_mt(grid, V, state, params, n_threads):
+    """segment() by n_threads threads (slabs of z planes; same bits)."""
+    nx, ny, nz = grid.dims
+    o = _c(grid.origin_mm, np.float64)
+    depth = np.empty((nz, nx), dtype=np.int16)
+    mean = np.empty((params.n_half, nz, nx), dtype=np.float32)
+    mx = np.empty((params.n_half, nz, nx), dtype=np.float32)
+    lib().orc_mt_segment(nx, ny, nz, _p(o), float(grid.voxel_mm), _p(_c(V, np.uint8)), _p(_c(state, np.uint8)),
+                         C.byref(params), _p(depth), _p(mean), _p(mx), int(n_threads))
+    return depth, mean, mx
 
 
 def segment(grid, V, state, params):

@@ -1,7 +1,8 @@
 """Compile the C oracle (test infrastructure) into oracle/_build/liborc.so with gcc.
 
 Flags: -O2 -ffp-contract=off -fno-fast-math so that every floating-point expression
-is evaluated in the order written (no FMA contraction).
+is evaluated in the order written (no FMA contraction); -fopenmp for the multi-thread
+schedule of the N-core CPU baseline (the single-thread functions use no threads).
 """
 import os
 import subprocess
@@ -18,7 +19,7 @@ def build(force: bool = False) -> str:
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

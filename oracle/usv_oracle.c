@@ -78,10 +78,18 @@ void orc_fold(const double *A, const double *C, double sx, double sy, const doub
  * only its rows rows[2f] .. rows[2f+1]: the cut image Img_C of Table I Step 5 /
  * Table II Step 4, compounded by Table I Step 6 / Table II Step 5.
  * ---------------------------------------------------------------------------------- */
-int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt, int *overflow,
-                           const uint8_t *frames, int W, int H, int64_t row_pitch, int64_t frame_pitch,
-                           const float *M, const uint8_t *mask, int n_frames,
-                           int32_t *stamp_buf, int32_t stamp, int64_t *n_distinct, const int32_t *rows) {
+/* The loops above restricted to the voxels of the planes i_z with i_z mod T = t (the
+ * whole grid for t = 0, T = 1).  A row none of whose planes is owned is skipped: along a
+ * row q_z = fl(fl(M[2][0] u) + c_z) does not decrease (or does not increase), because
+ * multiplying by a fixed factor and adding a fixed term are monotone under
+ * round-to-nearest, so the planes of a row's pixels lie between those of its two end
+ * pixels.  Used by the multi-thread variant below; the result does not depend on the
+ * split. */
+static int64_t ingest_nearest_slab(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt, int *overflow,
+                                   const uint8_t *frames, int W, int H, int64_t row_pitch, int64_t frame_pitch,
+                                   const float *M, const uint8_t *mask, int n_frames,
+                                   int32_t *stamp_buf, int32_t stamp, int64_t *n_distinct, const int32_t *rows,
+                                   int t, int T) {
   int64_t kept = 0;
   const float nf[3] = {(float)nx, (float)ny, (float)nz};
   for (int f = 0; f < n_frames; ++f) {
@@ -95,6 +103,16 @@ int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt,
         float t = m[r * 3 + 1] * fv;
         c[r] = t + m[r * 3 + 2];
       }
+      if (T > 1) {
+        float a0 = m[6] * 0.0f, a1 = m[6] * (float)(W - 1);
+        float qa = a0 + c[2], qb = a1 + c[2];
+        float lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+        if (!(hi >= 0.0f) || !(lo < nf[2])) continue;
+        int zlo = lo >= 0.0f ? (int)lo : 0, zhi = hi < nf[2] ? (int)hi : nz - 1;
+        int owned = 0;
+        for (int z = zlo; z <= zhi && !owned; ++z) owned = z % T == t;
+        if (!owned) continue;
+      }
       for (int u = 0; u < W; ++u) {
         if (mask && mask[(int64_t)v * W + u] == 0) continue;
         float fu = (float)u;
@@ -107,6 +125,7 @@ int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt,
         }
         if (!inside) continue;
         uint32_t ix = (uint32_t)q[0], iy = (uint32_t)q[1], iz = (uint32_t)q[2];
+        if (T > 1 && (int)(iz % (uint32_t)T) != t) continue;
         uint32_t idx = ix + (uint32_t)nx * (iy + (uint32_t)ny * iz);
         sum[idx] += (uint32_t)img[(int64_t)v * row_pitch + u];
         if (cnt[idx] == 0xFFFFu) *overflow = 1;
@@ -124,6 +143,14 @@ int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt,
   return kept;
 }
 
+int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt, int *overflow,
+                           const uint8_t *frames, int W, int H, int64_t row_pitch, int64_t frame_pitch,
+                           const float *M, const uint8_t *mask, int n_frames,
+                           int32_t *stamp_buf, int32_t stamp, int64_t *n_distinct, const int32_t *rows) {
+  return ingest_nearest_slab(nx, ny, nz, sum, cnt, overflow, frames, W, H, row_pitch, frame_pitch, M, mask,
+                             n_frames, stamp_buf, stamp, n_distinct, rows, 0, 1);
+}
+
 /* ------------------------------------------------------------------------------------
  * Normalise + PNN hole fill (Sec. II.C).
  *   V = cnt ? min(255, floor((2 sum + cnt) / (2 cnt))) : 0    (mean, rounded half up)
@@ -133,13 +160,12 @@ int64_t orc_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt,
  *   V' = floor((2 sum_N V + |N|) / (2 |N|)), state = FILLED (2); else V' = 0, EMPTY.
  * Returns the number of voxels with sum > 255 cnt (inconsistent, i.e. count wrapped).
  * ---------------------------------------------------------------------------------- */
-int64_t orc_finalize(int nx, int ny, int nz, const uint32_t *sum, const uint16_t *cnt, int fill_min,
-                     uint8_t *V_out, uint8_t *state_out) {
-  int64_t nvox = (int64_t)nx * ny * nz;
-  uint8_t *V = (uint8_t *)malloc((size_t)nvox);
-  uint8_t *meas = (uint8_t *)malloc((size_t)nvox);
+/* first pass over voxels i0 <= i < i1: the normalised value and the measured flag;
+ * returns the inconsistent voxels among them */
+static int64_t normalise_range(const uint32_t *sum, const uint16_t *cnt, int64_t i0, int64_t i1, uint8_t *V,
+                               uint8_t *meas) {
   int64_t bad = 0;
-  for (int64_t i = 0; i < nvox; ++i) {
+  for (int64_t i = i0; i < i1; ++i) {
     uint64_t c = cnt[i];
     uint64_t s = sum[i];
     if (s > 255u * c) ++bad;
@@ -152,7 +178,13 @@ int64_t orc_finalize(int nx, int ny, int nz, const uint32_t *sum, const uint16_t
       meas[i] = 0;
     }
   }
-  for (int z = 0; z < nz; ++z)
+  return bad;
+}
+
+/* second pass over planes z0 <= z < z1: copy measured voxels, fill empty ones */
+static void fill_planes(int nx, int ny, int nz, const uint8_t *V, const uint8_t *meas, int fill_min, int z0, int z1,
+                        uint8_t *V_out, uint8_t *state_out) {
+  for (int z = z0; z < z1; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int64_t i = (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
@@ -182,6 +214,15 @@ int64_t orc_finalize(int nx, int ny, int nz, const uint32_t *sum, const uint16_t
           state_out[i] = 0;
         }
       }
+}
+
+int64_t orc_finalize(int nx, int ny, int nz, const uint32_t *sum, const uint16_t *cnt, int fill_min,
+                     uint8_t *V_out, uint8_t *state_out) {
+  int64_t nvox = (int64_t)nx * ny * nz;
+  uint8_t *V = (uint8_t *)malloc((size_t)nvox);
+  uint8_t *meas = (uint8_t *)malloc((size_t)nvox);
+  int64_t bad = normalise_range(sum, cnt, 0, nvox, V, meas);
+  fill_planes(nx, ny, nz, V, meas, fill_min, 0, nz, V_out, state_out);
   free(V);
   free(meas);
   return bad;
@@ -218,68 +259,75 @@ static int cmp_i32(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
-void orc_segment(int nx, int ny, int nz, const double *origin, double s, const uint8_t *V,
-                 const uint8_t *state, const orc_seg_params *p, int16_t *depth, float *mean_out,
-                 float *max_out) {
-  int64_t plane = (int64_t)nx * nz;
-  int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)plane);
-  if (p->mode == 0) {
-    int32_t *raw = (int32_t *)malloc(sizeof(int32_t) * (size_t)plane);
-    for (int z = 0; z < nz; ++z)
-      for (int x = 0; x < nx; ++x) {
-        int32_t best = -1;
-        int64_t best_s = 0;
-        for (int y = p->y_lo; y <= ny - 1 - p->k; ++y) {
-          int64_t here = V[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z)];
-          int64_t below = 0;
-          for (int j = 1; j <= p->k; ++j)
-            below += V[(int64_t)x + (int64_t)nx * ((int64_t)(y + j) + (int64_t)ny * z)];
-          int64_t sc = (int64_t)p->k * here - below;
-          if (here >= p->tau_I && sc >= (int64_t)p->k * p->tau_G) {
-            if (best < 0 || sc >= best_s) {
-              best = y;
-              best_s = sc;
-            }
+/* ALG2 raw contour depth of the columns of planes z0 <= z < z1 */
+static void contour_planes(int nx, int ny, const uint8_t *V, const orc_seg_params *p, int z0, int z1, int32_t *raw) {
+  for (int z = z0; z < z1; ++z)
+    for (int x = 0; x < nx; ++x) {
+      int32_t best = -1;
+      int64_t best_s = 0;
+      for (int y = p->y_lo; y <= ny - 1 - p->k; ++y) {
+        int64_t here = V[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z)];
+        int64_t below = 0;
+        for (int j = 1; j <= p->k; ++j)
+          below += V[(int64_t)x + (int64_t)nx * ((int64_t)(y + j) + (int64_t)ny * z)];
+        int64_t sc = (int64_t)p->k * here - below;
+        if (here >= p->tau_I && sc >= (int64_t)p->k * p->tau_G) {
+          if (best < 0 || sc >= best_s) {
+            best = y;
+            best_s = sc;
           }
         }
-        raw[(int64_t)z * nx + x] = best;
       }
-    int32_t *win = (int32_t *)malloc(sizeof(int32_t) * (size_t)((2 * p->r + 1) * (2 * p->r + 1)));
-    for (int z = 0; z < nz; ++z)
-      for (int x = 0; x < nx; ++x) {
-        int n = 0;
-        for (int dz = -p->r; dz <= p->r; ++dz)
-          for (int dx = -p->r; dx <= p->r; ++dx) {
-            int xx = x + dx, zz = z + dz;
-            if (xx < 0 || zz < 0 || xx >= nx || zz >= nz) continue;
-            int32_t v = raw[(int64_t)zz * nx + xx];
-            if (v >= 0) win[n++] = v;
-          }
-        if (n == 0) {
-          d[(int64_t)z * nx + x] = p->fallback_y;
-        } else {
-          qsort(win, (size_t)n, sizeof(int32_t), cmp_i32);
-          d[(int64_t)z * nx + x] = win[(n - 1) / 2];
-        }
-      }
-    free(win);
-    free(raw);
-  } else {
-    for (int z = 0; z < nz; ++z) {
-      double cut;
-      if (p->mode == 1) {
-        double zc = origin[2] + ((double)z + 0.5) * s;
-        double sigma = fabs(zc - p->z1_mm);
-        cut = p->K * fabs(sigma - p->L_mm / 2.0) + p->D_mm;
-      } else {
-        cut = p->D_mm;
-      }
-      double yy = floor((p->yref_mm + cut - origin[1]) / s);
-      int32_t dz = yy < 0.0 ? 0 : (yy > (double)(ny - 1) ? ny - 1 : (int32_t)yy);
-      for (int x = 0; x < nx; ++x) d[(int64_t)z * nx + x] = dz;
+      raw[(int64_t)z * nx + x] = best;
     }
+}
+
+/* ALG2 median of the raw depths around the columns of planes z0 <= z < z1 */
+static void median_planes(int nx, int nz, const int32_t *raw, const orc_seg_params *p, int z0, int z1, int32_t *d) {
+  int32_t *win = (int32_t *)malloc(sizeof(int32_t) * (size_t)((2 * p->r + 1) * (2 * p->r + 1)));
+  for (int z = z0; z < z1; ++z)
+    for (int x = 0; x < nx; ++x) {
+      int n = 0;
+      for (int dz = -p->r; dz <= p->r; ++dz)
+        for (int dx = -p->r; dx <= p->r; ++dx) {
+          int xx = x + dx, zz = z + dz;
+          if (xx < 0 || zz < 0 || xx >= nx || zz >= nz) continue;
+          int32_t v = raw[(int64_t)zz * nx + xx];
+          if (v >= 0) win[n++] = v;
+        }
+      if (n == 0) {
+        d[(int64_t)z * nx + x] = p->fallback_y;
+      } else {
+        qsort(win, (size_t)n, sizeof(int32_t), cmp_i32);
+        d[(int64_t)z * nx + x] = win[(n - 1) / 2];
+      }
+    }
+  free(win);
+}
+
+/* ALG1 / FIXED depth of the columns of planes z0 <= z < z1 */
+static void pose_depth_planes(int nx, int ny, const double *origin, double s, const orc_seg_params *p, int z0, int z1,
+                              int32_t *d) {
+  for (int z = z0; z < z1; ++z) {
+    double cut;
+    if (p->mode == 1) {
+      double zc = origin[2] + ((double)z + 0.5) * s;
+      double sigma = fabs(zc - p->z1_mm);
+      cut = p->K * fabs(sigma - p->L_mm / 2.0) + p->D_mm;
+    } else {
+      cut = p->D_mm;
+    }
+    double yy = floor((p->yref_mm + cut - origin[1]) / s);
+    int32_t dz = yy < 0.0 ? 0 : (yy > (double)(ny - 1) ? ny - 1 : (int32_t)yy);
+    for (int x = 0; x < nx; ++x) d[(int64_t)z * nx + x] = dz;
   }
-  for (int z = 0; z < nz; ++z)
+}
+
+/* depth map and slab statistics of the columns of planes z0 <= z < z1 */
+static void slab_planes(int nx, int ny, int nz, const uint8_t *V, const uint8_t *state, const orc_seg_params *p,
+                        const int32_t *d, int z0, int z1, int16_t *depth, float *mean_out, float *max_out) {
+  int64_t plane = (int64_t)nx * nz;
+  for (int z = z0; z < z1; ++z)
     for (int x = 0; x < nx; ++x) {
       int32_t dd = d[(int64_t)z * nx + x];
       depth[(int64_t)z * nx + x] = (int16_t)dd;
@@ -300,6 +348,99 @@ void orc_segment(int nx, int ny, int nz, const double *origin, double s, const u
         max_out[o] = c ? (float)m : 0.0f;
       }
     }
+}
+
+void orc_segment(int nx, int ny, int nz, const double *origin, double s, const uint8_t *V,
+                 const uint8_t *state, const orc_seg_params *p, int16_t *depth, float *mean_out,
+                 float *max_out) {
+  int64_t plane = (int64_t)nx * nz;
+  int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)plane);
+  if (p->mode == 0) {
+    int32_t *raw = (int32_t *)malloc(sizeof(int32_t) * (size_t)plane);
+    contour_planes(nx, ny, V, p, 0, nz, raw);
+    median_planes(nx, nz, raw, p, 0, nz, d);
+    free(raw);
+  } else {
+    pose_depth_planes(nx, ny, origin, s, p, 0, nz, d);
+  }
+  slab_planes(nx, ny, nz, V, state, p, d, 0, nz, depth, mean_out, max_out);
+  free(d);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Multi-thread schedule of the same loops (the N-core CPU baseline).  Ingest: thread t of
+ * T owns the planes z with z mod T = t (interleaved, so that the few planes one call of
+ * consecutive frames reaches are shared by all threads) and alone writes their
+ * accumulators, so no two threads write one location and integer sums are the same in
+ * any order.  Normalise, hole fill, depth and slab statistics: thread t owns the planes
+ * [t nz / T, (t+1) nz / T) and writes only their values and outputs.  Every voxel's
+ * arithmetic is the single-thread oracle's.
+ * ---------------------------------------------------------------------------------- */
+static int slab_begin(int t, int T, int nz) { return (int)(((int64_t)t * nz) / T); }
+
+int64_t orc_mt_ingest_nearest(int nx, int ny, int nz, uint32_t *sum, uint16_t *cnt, int *overflow,
+                              const uint8_t *frames, int W, int H, int64_t row_pitch, int64_t frame_pitch,
+                              const float *M, const uint8_t *mask, int n_frames, int n_threads) {
+  int64_t kept = 0;
+  int T = n_threads < 1 ? 1 : n_threads;
+#pragma omp parallel for num_threads(T) schedule(static, 1) reduction(+ : kept)
+  for (int t = 0; t < T; ++t) {
+    int ov = 0;
+    int64_t nd = 0;
+    kept += ingest_nearest_slab(nx, ny, nz, sum, cnt, &ov, frames, W, H, row_pitch, frame_pitch, M, mask,
+                                n_frames, 0, 0, &nd, 0, t, T);
+    if (ov) {
+#pragma omp atomic write
+      *overflow = 1;
+    }
+  }
+  return kept;
+}
+
+int64_t orc_mt_finalize(int nx, int ny, int nz, const uint32_t *sum, const uint16_t *cnt, int fill_min,
+                        uint8_t *V_out, uint8_t *state_out, int n_threads) {
+  int64_t plane = (int64_t)nx * ny, bad = 0;
+  uint8_t *V = (uint8_t *)malloc((size_t)(plane * nz));
+  uint8_t *meas = (uint8_t *)malloc((size_t)(plane * nz));
+  int T = n_threads < 1 ? 1 : n_threads;
+#pragma omp parallel num_threads(T) reduction(+ : bad)
+  {
+#pragma omp for schedule(static, 1)
+    for (int t = 0; t < T; ++t)
+      bad += normalise_range(sum, cnt, plane * slab_begin(t, T, nz), plane * slab_begin(t + 1, T, nz), V, meas);
+#pragma omp for schedule(static, 1)
+    for (int t = 0; t < T; ++t)
+      fill_planes(nx, ny, nz, V, meas, fill_min, slab_begin(t, T, nz), slab_begin(t + 1, T, nz), V_out, state_out);
+  }
+  free(V);
+  free(meas);
+  return bad;
+}
+
+void orc_mt_segment(int nx, int ny, int nz, const double *origin, double s, const uint8_t *V,
+                    const uint8_t *state, const orc_seg_params *p, int16_t *depth, float *mean_out,
+                    float *max_out, int n_threads) {
+  int64_t plane = (int64_t)nx * nz;
+  int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)plane);
+  int32_t *raw = (int32_t *)malloc(sizeof(int32_t) * (size_t)plane);
+  int T = n_threads < 1 ? 1 : n_threads;
+#pragma omp parallel num_threads(T)
+  {
+    if (p->mode == 0) {
+#pragma omp for schedule(static, 1)
+      for (int t = 0; t < T; ++t) contour_planes(nx, ny, V, p, slab_begin(t, T, nz), slab_begin(t + 1, T, nz), raw);
+#pragma omp for schedule(static, 1)
+      for (int t = 0; t < T; ++t) median_planes(nx, nz, raw, p, slab_begin(t, T, nz), slab_begin(t + 1, T, nz), d);
+    } else {
+#pragma omp for schedule(static, 1)
+      for (int t = 0; t < T; ++t)
+        pose_depth_planes(nx, ny, origin, s, p, slab_begin(t, T, nz), slab_begin(t + 1, T, nz), d);
+    }
+#pragma omp for schedule(static, 1)
+    for (int t = 0; t < T; ++t)
+      slab_planes(nx, ny, nz, V, state, p, d, slab_begin(t, T, nz), slab_begin(t + 1, T, nz), depth, mean_out, max_out);
+  }
+  free(raw);
   free(d);
 }
 
