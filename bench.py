@@ -53,34 +53,78 @@ _SWEEP = None
 
 
 def _distinct_worker(q):
-    """Oracle pass over the whole sweep counting, per 64-frame call, the kept pixels and the
-    distinct voxels touched (the accumulator traffic a perfect merge still has to move)."""
+    """Oracle pass over the whole sweep counting, per 64-frame call, the kept pixels, the
+    distinct voxels touched and the distinct 64-byte accumulator segments they lie in (16
+    uint32 sums or 32 uint16 counts per segment): the accumulator traffic and the atomic
+    requests that a perfect merge of the call still has to send."""
     import oracle
     d = _SWEEP
     acc = oracle.Accum(d["grid"])
+    prev = np.zeros_like(acc.cnt)
     out = []
     for c in range(0, d["frames"].shape[0], CHUNK):
         kept, U = acc.ingest(d["frames"][c:c + CHUNK], d["poses"][c:c + CHUNK], d["probe"], count_distinct=True)
-        out.append((kept, U))
+        idx = np.flatnonzero(acc.cnt != prev)       # voxels this call touched (no count wraps here)
+        prev[idx] = acc.cnt[idx]
+        out.append((kept, U, int(np.unique(idx >> 4).size), int(np.unique(idx >> 5).size)))
     q.put(out)
 
 
-def time_oracle_step(d, seg, min_seconds=10.0, max_reps=3):
-    """CPU baseline: the oracle as it stands, same step, one host thread; the step is
-    repeated until about min_seconds of CPU work have run.  Returns (seconds per step,
-    repetitions)."""
+def time_oracle_step(d, seg, threads=1, min_seconds=10.0, max_reps=3):
+    """CPU baseline: the oracle as it stands, same step (calls of 64 frames, normalise +
+    hole fill, ALG2 depth + slabs); threads > 1 runs its multi-thread schedule (threads
+    own z planes; same bits).  The step is repeated until about min_seconds of CPU work
+    have run.  Returns (seconds per step, repetitions)."""
     import oracle
     reps, total = 0, 0.0
+    prm = oracle.seg_params(mode=oracle.ALG2, **seg)
     while reps < max_reps and (reps == 0 or total < min_seconds):
         t0 = time.perf_counter()
         acc = oracle.Accum(d["grid"])
         for c in range(0, d["frames"].shape[0], CHUNK):
-            acc.ingest(d["frames"][c:c + CHUNK], d["poses"][c:c + CHUNK], d["probe"])
-        V, S, _ = oracle.finalize(d["grid"], acc.sum, acc.cnt)
-        oracle.segment(d["grid"], V, S, oracle.seg_params(mode=oracle.ALG2, **seg))
+            if threads > 1:
+                acc.ingest_mt(d["frames"][c:c + CHUNK], d["poses"][c:c + CHUNK], d["probe"], threads)
+            else:
+                acc.ingest(d["frames"][c:c + CHUNK], d["poses"][c:c + CHUNK], d["probe"])
+        if threads > 1:
+            V, S, _ = oracle.finalize_mt(d["grid"], acc.sum, acc.cnt, threads)
+            oracle.segment_mt(d["grid"], V, S, prm, threads)
+        else:
+            V, S, _ = oracle.finalize(d["grid"], acc.sum, acc.cnt)
+            oracle.segment(d["grid"], V, S, prm)
         total += time.perf_counter() - t0
         reps += 1
     return total / reps, reps
+
+
+def time_oracle_batched(plan, frames4, threads, per_sweep=100):
+    """CPU baseline of the batched workload: the first per_sweep frames of every sweep
+    ingested by the oracle (calls of 64, each sweep into its own grid).  Returns frames/s."""
+    import oracle
+    t0 = time.perf_counter()
+    n = 0
+    for sw, fr in zip(plan, frames4):
+        acc = oracle.Accum(sw["grid"])
+        m = min(per_sweep, sw["F"])
+        for c in range(0, m, CHUNK):
+            k = min(CHUNK, m - c)
+            acc.ingest_mt(fr[c:c + k], sw["poses"][c:c + k], sw["probe"], threads)
+        n += m
+    return n / (time.perf_counter() - t0), n
+
+
+def time_oracle_splat(d5, n=128):
+    """CPU baseline of the differentiable step in FP64 (the oracle, one thread): forward
+    splat of the first n frames into the four volumes, overlap loss with its volume
+    gradients, backward to intensities and poses.  Returns (frames/s, seconds)."""
+    import oracle
+    g, p = d5["grid"], d5["probe"]
+    t0 = time.perf_counter()
+    vols = oracle.splat_forward(g, d5["I"][:n], d5["Tstar"][:n], d5["xi"][:n], p)
+    _, G = oracle.overlap_loss(vols)
+    oracle.splat_backward(g, d5["I"][:n], d5["Tstar"][:n], d5["xi"][:n], p, G)
+    dt = time.perf_counter() - t0
+    return n / dt, dt
 
 
 def counters_record(src_hash, tile):
@@ -161,9 +205,9 @@ def ingest_source_hash():
     return h.hexdigest()
 
 
-def bench_splat(torch, usv, steps):
+def bench_splat(torch, usv, steps, d=None):
     import synth
-    d = synth.cfg5()
+    d = synth.cfg5() if d is None else d
     g = d["grid"]
     F = d["I"].shape[0]
     ctx = usv.SplatContext(g.dims, g.origin_mm, g.voxel_mm, d["probe"].width, d["probe"].height,
@@ -386,24 +430,29 @@ def bench_realtime(torch, usv, d, render_every=10, n_upd=30):
     return rate, float(np.median(upd)) * 1e3
 
 
-def bench_batched(torch, usv, steps):
-    import synth
-    plan = synth.cfg4_plan()
-    banks = {True: synth.frame_bank(True), False: synth.frame_bank(False)}
+def bench_batched(torch, usv, plan, frames4, steps):
+    """Batched workload: the 16 sweeps of uneven length (linear and convex probes, each
+    with its own grid) with their own distinct frames, compounded by one batched launch
+    per pass.  Each probe type is autotuned first on 256 of its frames.  Returns (frames/s,
+    ms per pass, frames, in-mask pixel bytes per pass)."""
     jobs = []
     total = 0
-    for sw in plan:
+    px_bytes = 0
+    tuned = {}
+    for sw, fr_h in zip(plan, frames4):
         p, g = sw["probe"], sw["grid"]
         vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
         pid = vol.add_probe(p.width, p.height, p.pixel_mm, None, p.mask)
-        bank = torch.from_numpy(banks[sw["linear"]]).cuda()
-        F = sw["F"]
-        fr = torch.empty((F, p.height, p.width), dtype=torch.uint8, device="cuda")
-        for k in range(0, F, bank.shape[0]):
-            n = min(bank.shape[0], F - k)
-            fr[k:k + n] = bank[:n]
+        fr = torch.from_numpy(fr_h).cuda()
+        key = sw["linear"]
+        if key not in tuned:
+            tuned[key] = vol.autotune(pid, fr[:256], sw["poses"][:256], None)
+        else:
+            vol.set_tiling(pid, *tuned[key])
         jobs.append((vol, pid, fr, sw["poses"]))
-        total += F
+        total += sw["F"]
+        inside = p.width * p.height if p.mask is None else int((p.mask != 0).sum())
+        px_bytes += sw["F"] * inside
     usv.ingest_batched(jobs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -416,8 +465,87 @@ def bench_batched(torch, usv, steps):
     for j in jobs:
         if j[0].status() != 0:
             raise RuntimeError("batched ingest reported an error")
-    return total / dt, dt * 1e3, total
+    for j in jobs:
+        j[0].close()
+    return total / dt, dt * 1e3, total, px_bytes
 
+
+def bench_pinned(torch, usv, d, reps=2):
+    """The whole-spine step fed from pinned host memory: each call's 64 frames are copied
+    host -> device (PCIe) into a ring of three device slots on the volume's stream, then
+    ingested (launches on that stream, after their copy); then finalize + segment.
+    Returns (frames/s, ms per step)."""
+    g, p = d["grid"], d["probe"]
+    F = d["frames"].shape[0]
+    host = torch.from_numpy(d["frames"]).pin_memory()
+    ring = torch.empty((3, CHUNK, p.height, p.width), dtype=torch.uint8, device="cuda")
+    vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+    pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+    prm = usv.seg_params(mode=usv.SEG_ALG2, **SEG)
+    P = [np.ascontiguousarray(d["poses"][c:c + CHUNK]) for c in range(0, F, CHUNK)]
+
+    def step():
+        vol.reset()
+        for i, c in enumerate(range(0, F, CHUNK)):
+            n = min(CHUNK, F - c)
+            slot = ring[i % 3, :n]
+            slot.copy_(host[c:c + n], non_blocking=True)
+            vol.ingest(pid, slot, P[i])
+        V, S = vol.finalize()
+        vol.segment_project(prm, V, S)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    if vol.status() != 0:
+        raise RuntimeError("pinned-host step reported an error")
+    vol.close()
+    return F / dt, dt * 1e3
+
+
+def bench_cfg1(torch, usv, steps=50):
+    """Tiny plain sweep (64 frames of 128 x 96 into 64 x 64 x 96): reset, one ingest call,
+    finalize, ALG2 depth + slabs, per step; launch-bound.  Also the depth + slab pass on
+    that volume alone.  Returns (frames/s, ms per step, ms of segment_project alone)."""
+    import synth
+    d = synth.cfg1()
+    g, p = d["grid"], d["probe"]
+    vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
+    pid = vol.add_probe(p.width, p.height, p.pixel_mm)
+    fr = torch.from_numpy(d["frames"]).cuda()
+    prm = usv.seg_params(mode=usv.SEG_ALG2, r=2, fallback_y=20, half=(2, 5, 10))
+    nx, ny, nz = g.dims
+    V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    S = torch.empty_like(V)
+    out = (torch.empty((nz, nx), dtype=torch.int16, device="cuda"),
+           torch.empty((3, nz, nx), dtype=torch.float32, device="cuda"),
+           torch.empty((3, nz, nx), dtype=torch.float32, device="cuda"))
+
+    def step():
+        vol.reset()
+        vol.ingest(pid, fr, d["poses"])
+        vol.finalize(out=(V, S))
+        vol.segment_project(prm, V, S, out)
+
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        vol.segment_project(prm, V, S, out)
+    torch.cuda.synchronize()
+    seg_ms = (time.perf_counter() - t0) / steps * 1e3
+    vol.close()
+    return 64 / dt, dt * 1e3, seg_ms
 
 def main():
     ap = argparse.ArgumentParser()
@@ -464,6 +592,17 @@ def main():
             np.savez(args.cache, frames=d["frames"], poses=d["poses"])
     print("[bench] generated in %.1f s" % (time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
+    # the batched and differentiable workloads are generated here too, before any GPU call
+    # (the generator forks worker processes)
+    plan4 = frames4 = d5 = None
+    if not args.no_extras and not args.profile_pass:
+        t_gen = time.perf_counter()
+        plan4 = synth.cfg4_plan()
+        frames4 = synth.cfg4_frames(plan4)
+        d5 = synth.cfg5()
+        print("[bench] batched + differentiable workloads generated in %.1f s" % (time.perf_counter() - t_gen),
+              file=sys.stderr, flush=True)
+
     # the oracle's distinct-voxel pass runs in a child forked before any GPU call
     q = None
     proc = None
@@ -479,10 +618,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.extras_only:
-        out = {"extras_only": True, "fwd_bwd": bench_splat(torch, usv, 3),
+        out = {"extras_only": True, "fwd_bwd": bench_splat(torch, usv, 3, d5),
                "graph": bench_graph(torch, usv, d, n=128, n_lat=32),
                "refine": bench_refine(torch, usv, 20),
-               "batched": bench_batched(torch, usv, 1)}
+               "batched": bench_batched(torch, usv, plan4, frames4, 1)}
         g, p = d["grid"], d["probe"]
         frames = torch.from_numpy(d["frames"]).cuda()
         vol = usv.Volume(g.dims, g.origin_mm, g.voxel_mm)
@@ -577,6 +716,17 @@ def main():
     ms_step = (t1 - t0) * 1e3 / steps
     # per-phase times from extra steps with events (not part of the timed region)
     phase = np.zeros(3) if args.profile_pass else phase_steps(3)
+    # the same step timed by HIP events on the volume's stream: 2 warm-up + 10 timed runs
+    ev_ms = []
+    if not args.profile_pass:
+        for i in range(12):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step()
+            e1.record()
+            e1.synchronize()
+            if i >= 2:
+                ev_ms.append(e0.elapsed_time(e1))
     value = F / (ms_step / 1e3)
     print("[bench] %.3f ms/step  ingest %.3f  finalize %.3f  segment %.3f ms  tile %s  host submit %.3f ms/step" %
           (ms_step, phase[0], phase[1], phase[2], tile, 1e3 * float(np.median(host_submit))), file=sys.stderr,
@@ -604,34 +754,42 @@ def main():
     proc.join(timeout=60)
     n_pix = 0
     U = 0
-    for (kept, u), (_, _, _, n) in zip(per_chunk, chunks):
+    segs = 0
+    for (kept, u, ss, cs), (_, _, _, n) in zip(per_chunk, chunks):
         n_pix += n * p.width * p.height
         U += u
+        segs += ss + cs
     alg_bytes = n_pix * 1 + F * 36 + 12 * U
     # distinct voxels are counted per 64-frame call; with smaller launches this undercounts
     # the accumulator bytes (a conservative roofline)
-    achieved = alg_bytes / n_kernel / (per_launch_ms * 1e-3) / 1e9
+    bytes_launch = alg_bytes / n_kernel
+    segs_launch = segs / n_kernel
+    achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    hbm_floor_ms = bytes_launch / (HBM_PEAK_GBS * 1e9) * 1e3
+    atomic_floor_ms = segs_launch / ATOMIC_REQ_RATE * 1e3
     rec = counters_record(ingest_source_hash(), tile)
     traffic = rec.get("hbm_bytes_per_launch") if rec else None
-    atomic = None
-    if rec and rec.get("atomic_requests_per_launch"):
-        floor_ms = rec["atomic_requests_per_launch"] / ATOMIC_REQ_RATE * 1e3
-        atomic = {"requests_per_launch": rec["atomic_requests_per_launch"], "rate_per_s": ATOMIC_REQ_RATE,
-                  "floor_ms": round(floor_ms, 5), "frac": round(floor_ms / per_launch_ms, 4),
-                  "frac_overlapped": round(floor_ms / overlapped_launch_ms, 4)}
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    meas_req = rec.get("atomic_requests_per_launch") if rec else None
+    roof = {"bound": "hbm" if hbm_floor_ms >= atomic_floor_ms else "atomic",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ingest_kernel (PNN scatter, %d frames per launch)" % frames_per_launch,
-            "alg_bytes_per_launch": int(alg_bytes / n_kernel), "launch_ms": round(per_launch_ms, 5),
+            "alg_bytes_per_launch": int(bytes_launch), "launch_ms": round(per_launch_ms, 5),
             "distinct_voxels_per_launch": int(U / n_kernel),
+            "floors_ms": {"hbm": round(hbm_floor_ms, 5), "atomic": round(atomic_floor_ms, 5)},
+            "frac_of_max_floor": round(max(hbm_floor_ms, atomic_floor_ms) / per_launch_ms, 4),
+            "atomic": {"alg_segments_per_launch": int(segs_launch),
+                       "measured_requests_per_launch": meas_req,
+                       "request_excess": round(meas_req / segs_launch, 2) if meas_req else None,
+                       "rate_per_s": ATOMIC_REQ_RATE,
+                       "rate_source": "measured by microbench/atomic_rate (not a published figure)"},
             "overlapped": {"ingest_phase_ms": round(phase[0], 4), "ms_per_launch": round(overlapped_launch_ms, 5),
-                           "achieved": round(alg_bytes / n_kernel / (overlapped_launch_ms * 1e-3) / 1e9, 1)},
-            "atomic_request_floor": atomic}
+                           "achieved": round(bytes_launch / (overlapped_launch_ms * 1e-3) / 1e9, 1)}}
 
     extras = {}
     if not args.no_extras:
         try:
-            fps, ms = bench_splat(torch, usv, max(3, min(args.steps, 10)))
+            fps, ms = bench_splat(torch, usv, max(3, min(args.steps, 10)), d5)
             extras["fwd_bwd_frames_per_s"] = round(fps, 1)
             extras["fwd_bwd_ms_per_step"] = round(ms, 3)
         except Exception as e:  # report, do not hide
@@ -675,21 +833,56 @@ def main():
         except Exception as e:
             extras["realtime_error"] = repr(e)
         try:
-            fps, ms, tot = bench_batched(torch, usv, max(2, min(args.steps, 5)))
+            fps, ms, tot, pxb = bench_batched(torch, usv, plan4, frames4, max(2, min(args.steps, 5)))
             extras["batched_frames_per_s"] = round(fps, 1)
             extras["batched_ms_per_pass"] = round(ms, 3)
             extras["batched_frames"] = tot
+            extras["batched_pixel_GBps"] = round(pxb / (ms * 1e-3) / 1e9, 1)
+            extras["batched_hbm_frac_pixels_only"] = round(pxb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         except Exception as e:
             extras["batched_error"] = repr(e)
+        try:
+            fps, ms = bench_pinned(torch, usv, d)
+            extras["pinned_host_frames_per_s"] = round(fps, 1)
+            extras["pinned_host_ms_per_step"] = round(ms, 3)
+        except Exception as e:
+            extras["pinned_host_error"] = repr(e)
+        try:
+            fps, ms, seg_ms = bench_cfg1(torch, usv)
+            extras["cfg1_frames_per_s"] = round(fps, 1)
+            extras["cfg1_ms_per_step"] = round(ms, 4)
+            extras["cfg3_segment_ms"] = {"whole_spine_grid": round(phase[2], 4), "cfg1_grid": round(seg_ms, 4)}
+        except Exception as e:
+            extras["cfg1_error"] = repr(e)
 
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on the same step", file=sys.stderr, flush=True)
-        t_cpu, reps = time_oracle_step(d, SEG)
-        cpu = {"value": round(F / t_cpu, 2), "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": "the full step (3600 frames in 57 calls + finalize + ALG2 segment/projection), "
-                         "%d repetitions, single thread, %s" % (reps, cpu_model()),
-               "seconds": round(t_cpu, 2), "host_nproc": os.cpu_count()}
+        nproc = os.cpu_count() or 1
+        threads = max(1, min(nproc, int(os.environ.get("OMP_NUM_THREADS", nproc))))
+        t_mt, reps_mt = time_oracle_step(d, SEG, threads=threads, min_seconds=5.0, max_reps=2)
+        t_1, reps_1 = time_oracle_step(d, SEG, threads=1, min_seconds=1.0, max_reps=1)
+        cpu = {"value": round(F / t_mt, 2), "unit": "frames/s", "cores": threads, "kind": "oracle",
+               "sample": "the full step (3600 frames in 57 calls + normalise/fill + ALG2 depth and slabs), "
+                         "%d repetition(s), %d threads of the oracle's multi-thread schedule (threads own z "
+                         "planes; same bits as one thread), %s, %d logical CPUs" % (reps_mt, threads, cpu_model(), nproc),
+               "seconds": round(t_mt, 2), "host_nproc": nproc,
+               "single_thread": {"value": round(F / t_1, 2), "seconds": round(t_1, 2)}}
+        if plan4 is not None:
+            try:
+                fps4, n4 = time_oracle_batched(plan4, frames4, threads)
+                cpu["batched_frames_per_s"] = round(fps4, 2)
+                cpu["batched_sample"] = "first 100 frames of each of the 16 sweeps (%d frames), %d threads" % (n4, threads)
+            except Exception as e:
+                cpu["batched_error"] = repr(e)
+        if d5 is not None:
+            try:
+                fps5, t5 = time_oracle_splat(d5)
+                cpu["fwd_bwd_fp64_frames_per_s"] = round(fps5, 2)
+                cpu["fwd_bwd_fp64_sample"] = ("128 of the 512 frames: FP64 forward splat, overlap loss and "
+                                              "backward, one thread, %.1f s" % t5)
+            except Exception as e:
+                cpu["fwd_bwd_error"] = repr(e)
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "frames/s", "n_gpus": 1, "steps": steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -701,6 +894,8 @@ def main():
                       "ingest_streams": 1 if args.serial else 2, "parallelism": "single GPU"},
            "breakdown_ms": {"ingest": round(phase[0], 4), "finalize": round(phase[1], 4),
                             "segment_project": round(phase[2], 4)},
+           "event_ms_per_step": {"median": round(float(np.median(ev_ms)), 4), "min": round(float(np.min(ev_ms)), 4),
+                                 "runs": len(ev_ms), "warmup": 2},
            "roofline": roof, "cpu_baseline": cpu}
     out.update(extras)
     print(json.dumps(out))

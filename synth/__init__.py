@@ -290,6 +290,26 @@ def cfg4_plan(n_sweeps: int = 16, seed_cfg: int = 4):
     return plan
 
 
+def cfg4_frames(plan, count: Optional[int] = None, seed_cfg: int = 4, workers: Optional[int] = None):
+    """The frames of every sweep of a cfg4_plan (the first `count` of each, or all),
+    each imaged along its sweep's own path (the poses in plan[i]["poses"]): a list of
+    uint8 [F_i][H][W] arrays, zero outside a convex probe's fan.  One worker pool serves
+    all sweeps."""
+    items, shapes = [], []
+    for i, sw in enumerate(plan):
+        F, pr = sw["F"], sw["probe"]
+        m = F if count is None else min(count, F)
+        mask = None if pr.mask is None else np.ascontiguousarray(pr.mask, np.uint8).tobytes()
+        items += [(n, F, pr.width, pr.height, pr.pixel_mm[0], sw["length_mm"], seed_cfg, i, mask) for n in range(m)]
+        shapes.append((m, pr.height, pr.width))
+    outs = [np.empty(sh, dtype=np.uint8) for sh in shapes]
+    sweep_of = np.repeat(np.arange(len(plan)), [sh[0] for sh in shapes])
+    for (n, _, img), i in zip(_pool_map(_spine_frame, items, default_workers() if workers is None else workers),
+                              sweep_of):
+        outs[i][n] = img
+    return outs
+
+
 def frame_bank(linear: bool, n: int = 64, seed_cfg: int = 4):
     """A bank of n distinct frames of one probe type (speckle + phantom along a short
     straight path), used to fill the pixels of the batched sweeps."""
@@ -304,6 +324,17 @@ def frame_bank(linear: bool, n: int = 64, seed_cfg: int = 4):
 
 
 # --- config 5: differentiable splat ---------------------------------------------------------
+
+
+def _cfg5_frame(args):
+    n, T, W, H, px, centres, amps = args
+    X, Y, Z = pixel_world(T, W, H, px, px)
+    val = np.zeros((H, W))
+    for b in range(centres.shape[0]):
+        d2 = (X - centres[b, 0]) ** 2 + (Y - centres[b, 1]) ** 2 + (Z - centres[b, 2]) ** 2
+        val += amps[b] * np.exp(-d2 / (2.0 * 16.0))
+    val += 0.1 * speckle(rng(5, 1, n), (H, W))
+    return n, (np.minimum(val, 255.0) / 255.0).astype(np.float32)
 
 
 def cfg5(n_frames: int = 512, W: int = 320, H: int = 240, px: float = 0.4,
@@ -322,13 +353,9 @@ def cfg5(n_frames: int = 512, W: int = 320, H: int = 240, px: float = 0.4,
         T = np.eye(4)
         T[2, 3] = 0.25 + 0.5 * n
         Tstar[n] = T
-        X, Y, Z = pixel_world(T, W, H, px, px)
-        val = np.zeros((H, W))
-        for b in range(n_blobs):
-            d2 = (X - centres[b, 0]) ** 2 + (Y - centres[b, 1]) ** 2 + (Z - centres[b, 2]) ** 2
-            val += amps[b] * np.exp(-d2 / (2.0 * 16.0))
-        val += 0.1 * speckle(rng(5, 1, n), (H, W))
-        I[n] = (np.minimum(val, 255.0) / 255.0).astype(np.float32)
+    items = [(n, Tstar[n], W, H, px, centres, amps) for n in range(n_frames)]
+    for n, img in _pool_map(_cfg5_frame, items, default_workers()):
+        I[n] = img
     gp = rng(5, 3, 0)
     xi = np.concatenate([gp.uniform(-1.0, 1.0, size=(n_frames, 3)),
                          gp.uniform(-1.0, 1.0, size=(n_frames, 3)) * (math.pi / 180.0)], axis=1)
