@@ -145,31 +145,33 @@ def counters_record(src_hash, tile):
 ATOMIC_REQ_RATE = 23.0e9
 
 
-def counters_summary(fetch_db, write_db, out_json, atomic_db=None, tile=None):
+def _per_kernel(csv_path, counter=None):
+    """{kernel: {counter: (mean value per dispatch, dispatches)}} from a rocprofv3 --pmc
+    run in CSV form (run_counter_collection.csv); kernel names without namespaces and
+    arguments."""
+    import csv
+    agg = {}
+    for r in csv.DictReader(open(csv_path)):
+        if counter and r["Counter_Name"] != counter:
+            continue
+        k = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
+        a = agg.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+        a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return {k: {c: (sum(v.values()) / len(v), len(v)) for c, v in cs.items()} for k, cs in agg.items()}
+
+
+def counters_summary(fetch_csv, write_csv, out_json, atomic_csv=None, tile=None):
     """Summarise two rocprofv3 --pmc runs of `bench.py --profile-pass` (FETCH_SIZE, then
-    WRITE_SIZE; rocpd sqlite output) into HBM bytes per ingest launch.  Each counter is
-    scaled by what it reads for copy_u32_kernel, which the profile pass runs once on a
-    buffer of known size (the accumulator export), so the figure is in true bytes."""
-    import sqlite3
+    WRITE_SIZE; CSV output) into HBM bytes per ingest launch.  Each counter is scaled by
+    what it reads for copy_u32_kernel, which the profile pass runs once on a buffer of
+    known size (the accumulator export), so the figure is in true bytes."""
     import synth
     from paper_2412_00058_amd.usv import accumulator_bytes
 
-    def per_kernel(db, counter):
-        con = sqlite3.connect(db)
-        agg = {}
-        for name, cname, val, disp in con.execute(
-                "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
-            if cname != counter:
-                continue
-            k = name.replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
-            a = agg.setdefault(k, {})
-            a[disp] = a.get(disp, 0.0) + float(val)
-        return {k: (sum(v.values()) / len(v), len(v)) for k, v in agg.items()}
-
     g = synth.cfg2(count=0)["grid"]
     copy_bytes = accumulator_bytes(g.dims)
-    fetch = per_kernel(fetch_db, "FETCH_SIZE")
-    write = per_kernel(write_db, "WRITE_SIZE")
+    fetch = {k: v["FETCH_SIZE"] for k, v in _per_kernel(fetch_csv, "FETCH_SIZE").items()}
+    write = {k: v["WRITE_SIZE"] for k, v in _per_kernel(write_csv, "WRITE_SIZE").items()}
     f_copy, w_copy = fetch["copy_u32_kernel"][0] * 1024.0, write["copy_u32_kernel"][0] * 1024.0
     kf, kw = copy_bytes / f_copy, copy_bytes / w_copy
     f_ing, n_f = fetch["ingest_kernel"]
@@ -180,8 +182,8 @@ def counters_summary(fetch_db, write_db, out_json, atomic_db=None, tile=None):
            "copy_fetch_kib": round(f_copy / 1024.0, 1), "copy_write_kib": round(w_copy / 1024.0, 1),
            "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
            "hbm_bytes_per_launch": int(f_ing * 1024.0 * kf + w_ing * 1024.0 * kw)}
-    if atomic_db:
-        atom = per_kernel(atomic_db, "TCC_EA0_ATOMIC_sum")
+    if atomic_csv:
+        atom = {k: v["TCC_EA0_ATOMIC_sum"] for k, v in _per_kernel(atomic_csv, "TCC_EA0_ATOMIC_sum").items()}
         rec["atomic_requests_per_launch"] = int(atom["ingest_kernel"][0])
     for k in sorted(set(fetch) | set(write)):
         f = fetch.get(k, (0.0, 0))[0]
@@ -191,6 +193,51 @@ def counters_summary(fetch_db, write_db, out_json, atomic_db=None, tile=None):
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
+
+
+# wave64 VALU instructions the MI355X can issue per second: 256 CUs x 4 SIMDs, one wave64
+# instruction per 4 cycles per SIMD (16 lanes per cycle), 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def pmc_report(csv_paths, stats_csv, fetch_scale=2.0, write_scale=1.0):
+    """Per-kernel table of rocprofv3 counters (mean per dispatch) joined with the kernel
+    trace's mean duration: HBM bytes from FETCH_SIZE / WRITE_SIZE (KiB, scaled by the copy
+    calibration), device atomic requests, VALU instructions and their share of the chip's
+    VALU issue rate over the kernel's duration, LDS and SALU instructions, waves."""
+    import csv
+    dur = {}
+    for r in csv.DictReader(open(stats_csv)):
+        k = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
+        dur[k] = float(r["AverageNs"])
+    table = {}
+    for pth in csv_paths:
+        for k, cs in _per_kernel(pth).items():
+            table.setdefault(k, {}).update({c: v[0] for c, v in cs.items()})
+    lines = []
+    for k in sorted(table):
+        c = table[k]
+        parts = ["%-32s" % k]
+        ns = dur.get(k)
+        if ns:
+            parts.append("%9.1f us" % (ns / 1e3))
+        if "FETCH_SIZE" in c:
+            parts.append("fetch %8.2f MB" % (c["FETCH_SIZE"] * 1024 * fetch_scale / 1e6))
+        if "WRITE_SIZE" in c:
+            parts.append("write %8.2f MB" % (c["WRITE_SIZE"] * 1024 * write_scale / 1e6))
+        if "TCC_EA0_ATOMIC_sum" in c:
+            parts.append("atomic req %9.0f" % c["TCC_EA0_ATOMIC_sum"])
+        if "SQ_INSTS_VALU" in c:
+            parts.append("VALU insts %10.0f" % c["SQ_INSTS_VALU"])
+            if ns:
+                parts.append("VALU issue %5.1f%%" % (100.0 * c["SQ_INSTS_VALU"] / (ns * 1e-9 * VALU_ISSUE_PEAK)))
+        for name, lab in (("SQ_INSTS_LDS", "LDS"), ("SQ_INSTS_SALU", "SALU"), ("SQ_WAVES", "waves")):
+            if name in c:
+                parts.append("%s %9.0f" % (lab, c[name]))
+        if "SQ_ACTIVE_INST_VALU" in c and "SQ_BUSY_CU_CYCLES" in c and c["SQ_BUSY_CU_CYCLES"] > 0:
+            parts.append("VALU active/CU-busy %5.2f" % (c["SQ_ACTIVE_INST_VALU"] / c["SQ_BUSY_CU_CYCLES"]))
+        lines.append("  ".join(parts))
+    return "\n".join(lines)
 
 
 def ingest_source_hash():
@@ -547,6 +594,23 @@ def bench_cfg1(torch, usv, steps=50):
     vol.close()
     return 64 / dt, dt * 1e3, seg_ms
 
+def splat_pass(args):
+    """Three differentiable steps of the 512-frame workload for a profiler (no extras)."""
+    import synth
+    if args.cache5 and os.path.exists(args.cache5):
+        z = np.load(args.cache5, allow_pickle=False)
+        d5 = synth.cfg5(n_frames=0)
+        d5["I"], d5["Tstar"], d5["xi"] = z["I"], z["Tstar"], z["xi"]
+    else:
+        d5 = synth.cfg5()
+        if args.cache5:
+            np.savez(args.cache5, I=d5["I"], Tstar=d5["Tstar"], xi=d5["xi"])
+    import torch
+    import paper_2412_00058_amd as usv
+    fps, ms = bench_splat(torch, usv, 3, d5)
+    print(json.dumps({"splat_pass": True, "fwd_bwd_frames_per_s": round(fps, 1), "ms_per_step": round(ms, 3)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -562,9 +626,17 @@ def main():
     ap.add_argument("--cache", default=None,
                     help="load the generated sweep from this .npz (written there if missing); lets a profiled "
                          "run skip the generator's worker processes")
-    ap.add_argument("--counters-summary", nargs="+", metavar="DB", default=None,
-                    help="no GPU: summarise the rocprofv3 --pmc result databases of the profile pass "
+    ap.add_argument("--counters-summary", nargs="+", metavar="CSV", default=None,
+                    help="no GPU: summarise the rocprofv3 --pmc CSV results of the profile pass "
                          "(FETCH_SIZE, WRITE_SIZE[, TCC_EA0_ATOMIC_sum]) into profiles/ingest_cfg2_counters.json")
+    ap.add_argument("--pmc-report", nargs="+", metavar="CSV", default=None,
+                    help="no GPU: per-kernel counter table of rocprofv3 --pmc CSV results, joined with the "
+                         "kernel-trace statistics given by --stats")
+    ap.add_argument("--stats", default=None, help="rocprofv3 kernel_stats.csv for --pmc-report")
+    ap.add_argument("--splat-pass", action="store_true",
+                    help="for rocprofv3: three differentiable steps (forward, loss, backward) on the "
+                         "512-frame workload read from --cache5")
+    ap.add_argument("--cache5", default=None, help=".npz of the differentiable workload (written if missing)")
     ap.add_argument("--counters-tile", nargs=2, type=int, metavar=("W", "H"), default=None,
                     help="the ingest tile shape of the profiled pass (printed by it), stored with the summary")
     args = ap.parse_args()
@@ -572,6 +644,12 @@ def main():
         dbs = args.counters_summary
         counters_summary(dbs[0], dbs[1], os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json"),
                          dbs[2] if len(dbs) > 2 else None, args.counters_tile)
+        return
+    if args.pmc_report:
+        print(pmc_report(args.pmc_report, args.stats))
+        return
+    if args.splat_pass:
+        splat_pass(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on a single GPU, and sharding the "
