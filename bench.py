@@ -143,6 +143,10 @@ def counters_record(src_hash, tile):
 # device-scope atomic requests (64-byte segments per wave instruction) per second on the
 # MI355X, measured by microbench/atomic_rate (profiles/atomics_microbench.txt): 21.6-26.7 G
 ATOMIC_REQ_RATE = 23.0e9
+# plain VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the
+# published 157.3 TFLOP/s FP32 vector rate counts an FMA as two and packed math as two)
+ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+ALU_OPS_PER_PIXEL = 10
 
 
 def _per_kernel(csv_path, counter=None):
@@ -481,7 +485,8 @@ def bench_batched(torch, usv, plan, frames4, steps):
     """Batched workload: the 16 sweeps of uneven length (linear and convex probes, each
     with its own grid) with their own distinct frames, compounded by one batched launch
     per pass.  Each probe type is autotuned first on 256 of its frames.  Returns (frames/s,
-    ms per pass, frames, in-mask pixel bytes per pass)."""
+    ms per pass, frames, in-mask pixel bytes per pass, frames/s of the same sweeps through
+    plain calls of 64 frames with overlapped launches)."""
     jobs = []
     total = 0
     px_bytes = 0
@@ -509,12 +514,30 @@ def bench_batched(torch, usv, plan, frames4, steps):
         usv.ingest_batched(jobs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    # the same sweeps through plain calls of 64 frames (overlapped launches), for comparison
+    for j in jobs:
+        j[0].set_ingest_overlap(True)
+    tp = []
+    for _ in range(steps):
+        for j in jobs:
+            j[0].reset()
+            j[0].join()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for vol, pid, fr, P in jobs:
+            for c in range(0, fr.shape[0], CHUNK):
+                vol.ingest(pid, fr[c:c + CHUNK], P[c:c + CHUNK])
+        for j in jobs:
+            j[0].join()
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t1)
+    dtp = float(np.median(tp))
     for j in jobs:
         if j[0].status() != 0:
             raise RuntimeError("batched ingest reported an error")
     for j in jobs:
         j[0].close()
-    return total / dt, dt * 1e3, total, px_bytes
+    return total / dt, dt * 1e3, total, px_bytes, total / dtp
 
 
 def bench_pinned(torch, usv, d, reps=2):
@@ -848,21 +871,38 @@ def main():
     rec = counters_record(ingest_source_hash(), tile)
     traffic = rec.get("hbm_bytes_per_launch") if rec else None
     meas_req = rec.get("atomic_requests_per_launch") if rec else None
-    roof = {"bound": "hbm" if hbm_floor_ms >= atomic_floor_ms else "atomic",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+    # ALU floor: per kept pixel the method needs 3 FP32 adds (the per-column products and
+    # per-row constants are shared by a whole column / row), 3 float -> integer
+    # conversions, 2 multiply-adds for the linear voxel index and 2 integer adds (sum and
+    # count): 10 lane operations, against the chip's 39.3 T lane-operations/s
+    alu_ops_launch = ALU_OPS_PER_PIXEL * n_pix / n_kernel
+    alu_floor_ms = alu_ops_launch / ALU_PEAK_OPS * 1e3
+    floors = {"hbm": hbm_floor_ms, "atomic": atomic_floor_ms, "alu": alu_floor_ms}
+    bound = max(floors, key=floors.get)
+    if bound == "alu":
+        head = {"achieved": round(alu_ops_launch / (per_launch_ms * 1e-3) / 1e12, 2), "peak": ALU_PEAK_OPS / 1e12,
+                "unit": "TOP/s"}
+    elif bound == "hbm":
+        head = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        head = {"achieved": round(segs_launch / (per_launch_ms * 1e-3) / 1e9, 2), "peak": ATOMIC_REQ_RATE / 1e9,
+                "unit": "G requests/s"}
+    roof = {"bound": bound, **head, "frac": round(floors[bound] / per_launch_ms, 4), "traffic": traffic,
             "kernel": "ingest_kernel (PNN scatter, %d frames per launch)" % frames_per_launch,
-            "alg_bytes_per_launch": int(bytes_launch), "launch_ms": round(per_launch_ms, 5),
-            "distinct_voxels_per_launch": int(U / n_kernel),
-            "floors_ms": {"hbm": round(hbm_floor_ms, 5), "atomic": round(atomic_floor_ms, 5)},
-            "frac_of_max_floor": round(max(hbm_floor_ms, atomic_floor_ms) / per_launch_ms, 4),
+            "launch_ms": round(per_launch_ms, 5),
+            "floors_ms": {k: round(v, 5) for k, v in floors.items()},
+            "hbm": {"alg_bytes_per_launch": int(bytes_launch), "achieved_GBps": round(achieved, 1),
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "distinct_voxels_per_launch": int(U / n_kernel)},
+            "alu": {"alg_ops_per_pixel": ALU_OPS_PER_PIXEL, "alg_ops_per_launch": int(alu_ops_launch),
+                    "peak_ops_per_s": ALU_PEAK_OPS},
             "atomic": {"alg_segments_per_launch": int(segs_launch),
                        "measured_requests_per_launch": meas_req,
                        "request_excess": round(meas_req / segs_launch, 2) if meas_req else None,
                        "rate_per_s": ATOMIC_REQ_RATE,
                        "rate_source": "measured by microbench/atomic_rate (not a published figure)"},
             "overlapped": {"ingest_phase_ms": round(phase[0], 4), "ms_per_launch": round(overlapped_launch_ms, 5),
-                           "achieved": round(bytes_launch / (overlapped_launch_ms * 1e-3) / 1e9, 1)}}
+                           "frac": round(floors[bound] / overlapped_launch_ms, 4)}}
 
     extras = {}
     if not args.no_extras:
@@ -911,8 +951,9 @@ def main():
         except Exception as e:
             extras["realtime_error"] = repr(e)
         try:
-            fps, ms, tot, pxb = bench_batched(torch, usv, plan4, frames4, max(2, min(args.steps, 5)))
+            fps, ms, tot, pxb, fps_plain = bench_batched(torch, usv, plan4, frames4, max(2, min(args.steps, 5)))
             extras["batched_frames_per_s"] = round(fps, 1)
+            extras["batched_same_frames_plain_calls_frames_per_s"] = round(fps_plain, 1)
             extras["batched_ms_per_pass"] = round(ms, 3)
             extras["batched_frames"] = tot
             extras["batched_pixel_GBps"] = round(pxb / (ms * 1e-3) / 1e9, 1)

@@ -308,7 +308,8 @@ usv_status usv_vnn_destroy(usv_vnn *ctx);
 /* ---------------------------------------------------------------------------------
  * Batched multi-sweep ingest: n_sweeps independent (volume, probe, frames, poses)
  * jobs compounded by one kernel launch on the first volume's stream, one block per
- * (sweep, frame, tile) item of every sweep's current tiling (usv_autotune).  All
+ * (sweep, frame, tile) item of every sweep's current tiling (usv_autotune), the items of
+ * each XCD contiguous.  All
  * volumes must live on the same device.  Per sweep the result equals
  * usv_ingest_frames on that sweep alone (bit for bit).  dirty_out: n_sweeps boxes or
  * NULL.

@@ -428,12 +428,15 @@ __global__ __launch_bounds__(kBlock) void ingest_kernel_devm(SweepDesc d, const 
     run_block<false, true>(d, M, fidx, nullptr, nullptr, sm);
 }
 
-// Batched ingest: one launch over the flat (sweep, frame, tile) list of every sweep;
-// block b finds its sweep by binary search over the sweeps' first items (each sweep's
-// list starts at a multiple of 8 items so that tile columns stay on one XCD).
+// Batched ingest: one launch over the flat (sweep, frame, tile) list of every sweep, one
+// block per item.  Block b is the (b / 8)-th block on XCD b % 8 and takes item
+// (b % 8) per_xcd + b / 8, so each XCD works through a contiguous part of the list and
+// neighbouring tiles of a frame, which share the cache lines at their borders, are read
+// through one L2.  The block finds its sweep by binary search over the sweeps' first items.
 __global__ __launch_bounds__(kBlock) void ingest_batched_kernel(BatchLaunch a) {
   __shared__ __align__(16) Smem sm;
-  const int64_t it = blockIdx.x;
+  const int64_t it = (int64_t)(blockIdx.x & 7u) * a.per_xcd + (int64_t)(blockIdx.x >> 3);
+  if (it >= a.n_items) return;
   int lo = 0, hi = a.n_sweeps - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -532,10 +535,11 @@ hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t s) {
-  (void)n_blocks;
-  if (a.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ingest_batched_kernel, dim3((unsigned)a.n_items), dim3(kBlock), 0, s, a);
+hipError_t launch_ingest_batched(const BatchLaunch &a0, hipStream_t s) {
+  if (a0.n_items <= 0) return hipSuccess;
+  BatchLaunch a = a0;
+  a.per_xcd = (a.n_items + 7) / 8;
+  hipLaunchKernelGGL(ingest_batched_kernel, dim3((unsigned)(8 * a.per_xcd)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

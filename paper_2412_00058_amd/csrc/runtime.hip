@@ -1206,7 +1206,6 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
     std::memcpy(hf + fpos, fidx[e].data(), nf * sizeof(int32_t));
     hs[nsw++] = b;
     items += b.items_per_frame * (int64_t)nf;
-    items = (items + 7) / 8 * 8;   // next sweep starts on a multiple of 8 items (XCD alignment)
     fpos += nf;
   }
   if (items == 0) return USV_OK;
@@ -1236,7 +1235,7 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
   a.sweeps = (const BatchSweep *)owner->d_batch;
   a.n_sweeps = nsw;
   a.n_items = items;
-  st = check_hip(owner, launch_ingest_batched(a, (int)items, s), "batched launch");
+  st = check_hip(owner, launch_ingest_batched(a, s), "batched launch");
   if (st != USV_OK) return st;
   for (int32_t i = 1; i < n_sweeps; ++i) {
     if (vols[i]->stream == s) continue;

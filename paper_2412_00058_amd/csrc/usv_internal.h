@@ -79,12 +79,13 @@ struct BatchSweep {
 struct BatchLaunch {
   const BatchSweep *sweeps;   // device array
   int32_t n_sweeps;
-  int64_t n_items;            // one block per item; each sweep starts at a multiple of 8
+  int64_t n_items;            // (sweep, frame, tile) items, one block each
+  int64_t per_xcd;            // items per XCD (set by launch_ingest_batched)
 };
 
 // n_items = frames x tiles, one block per item
 hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s);
-hipError_t launch_ingest_batched(const BatchLaunch &a, int n_blocks, hipStream_t s);
+hipError_t launch_ingest_batched(const BatchLaunch &a, hipStream_t s);
 hipError_t launch_ingest_rows(const IngestLaunchRows &a, int n_items, hipStream_t s);
 hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t *fidx, int n_frames, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n_words, hipStream_t s);
