@@ -205,7 +205,10 @@ usv_status usv_finalize(usv_volume *vol, const usv_box *region, uint8_t *vol_u8_
 
 /* Bone depth + slab projection (Sec. II.D) of a finalized volume.  Outputs:
  * depth_dev int16 [nz][nx]; mean_dev and max_dev FP32 [n_half][nz][nx].  n_half 1..4,
- * half widths 0..255, k 1..64, r 0..8, y_lo >= 0, fallback_y in [0, ny). */
+ * half widths 0..255, k 1..64, r 0..8, y_lo >= 0, fallback_y in [0, ny) (USV_E_ARG
+ * otherwise).  USV_E_STATE if pixels were added to the volume (ingest, graph launch,
+ * batched ingest, import) after its last usv_finalize or usv_reset: the volume's
+ * outputs would not reflect them. */
 usv_status usv_segment_project(usv_volume *vol, const usv_seg_params *params, const uint8_t *vol_u8_dev,
                                const uint8_t *state_dev, int16_t *depth_dev, float *mean_dev, float *max_dev);
 

@@ -27,3 +27,14 @@ def build(force: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(force=True))
+
+
+def build_sanitized(out_path: str) -> str:
+    """The same source with AddressSanitizer and UndefinedBehaviorSanitizer (gcc): every
+    out-of-bounds access, use after free or undefined operation aborts.  Loaded by a
+    process started with the sanitizer runtime preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
+           "-fopenmp", "-fPIC", "-shared", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", "-o", out_path, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path

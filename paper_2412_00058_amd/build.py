@@ -37,5 +37,34 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out_path: str) -> str:
+    """libusv.so with its host code built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (each -fsanitize= applies to the host pass only; the gfx950 code is built as usual):
+    for checking the host runtime (argument validation, pose fold, boxes, tables) in a
+    process started with clang's sanitizer runtime preloaded."""
+    host = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-shared-libasan", "-g"]
+    flags = [f if f != "-O3" else "-O1" for f in FLAGS]
+    cmd = [HIPCC] + flags + host + ["-o", out_path] + [os.path.join(CSRC, s) for s in SOURCES]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the sanitized libusv.so")
+    return out_path
+
+
+def asan_runtime() -> str:
+    """clang's AddressSanitizer runtime that the sanitized library links against."""
+    import glob
+    base = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "llvm", "lib", "clang")
+    hits = sorted(glob.glob(os.path.join(base, "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so")
+    return hits[-1]
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -97,6 +97,7 @@ struct usv_volume {
   // side stream 1.
   hipEvent_t acc_ev = nullptr, zero_ev = nullptr;
   bool acc_quiet = false;      // nothing has touched the accumulators since acc_ev
+  bool unfinalized = false;    // pixels added (or accumulators imported) since the last finalize / reset
   bool zero_pending = false;   // side stream 1 has not yet waited for zero_ev
 };
 
@@ -311,7 +312,9 @@ usv_box grid_box(const usv_volume *v) {
 
 // Widen the touched box by a box some ingest may change (called before the launch).
 void touch(usv_volume *v, const usv_box &b) {
-  if (!box_empty(b)) box_union(v->touched, b.lo, b.hi);
+  if (box_empty(b)) return;
+  box_union(v->touched, b.lo, b.hi);
+  v->unfinalized = true;
 }
 
 // ---- tiling --------------------------------------------------------------------------
@@ -684,6 +687,7 @@ usv_status usv_reset(usv_volume *v) {
   if (st != USV_OK) return st;
   v->touched = empty_box();
   v->count_dirty = false;
+  v->unfinalized = false;
   return USV_OK;
 }
 
@@ -802,6 +806,7 @@ usv_status usv_import_accumulators(usv_volume *v, const void *src) {
     if (js != USV_OK) return js;
   }
   v->touched = grid_box(v);   // imported content may be anywhere
+  v->unfinalized = true;
   usv_status st = check_hip(v, launch_copy_u32((uint32_t *)v->acc, (const uint32_t *)src,
                                                (int64_t)(usv_accumulator_bytes_of(v) / 4), v->stream), "import");
   if (st != USV_OK) return st;
@@ -979,6 +984,7 @@ usv_status usv_finalize(usv_volume *v, const usv_box *region, uint8_t *vol_u8, u
     if (st != USV_OK) return st;
     v->acc_quiet = true;
   }
+  v->unfinalized = false;
   return USV_OK;
 }
 
@@ -990,6 +996,7 @@ usv_status usv_segment_project(usv_volume *v, const usv_seg_params *pr, const ui
     if (js != USV_OK) return js;
   }
   if (!seg_params_ok(pr, v->ny)) return fail(v, USV_E_ARG, "bad segmentation parameters");
+  if (v->unfinalized) return fail(v, USV_E_STATE, "pixels were added since the last finalize");
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   const SegArgs a = seg_args(pr, vol_u8, state, v->d_raw, depth, mean, max, v->nx, v->ny, v->nz, v->origin, v->s);
   return check_hip(v, launch_segment(a, v->stream), "segment launch");
@@ -1454,6 +1461,7 @@ usv_status usv_graph_launch(usv_graph *g, const uint8_t *frame_host, const doubl
   if (!frame_box(M, p.W, p.H, dims, lo, hi)) return USV_OK;
   if (dirty_out) box_union(*dirty_out, lo, hi);
   box_union(v->touched, lo, hi);
+  v->unfinalized = true;
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   const int k = g->next;
   if (g->used[k]) {

@@ -625,3 +625,34 @@ def test_splat_binding_checks():
         ref = o[k].reshape(-1)
         assert np.linalg.norm(v[k] - ref) <= 1e-5 * np.linalg.norm(ref)
     ctx.close()
+
+
+def test_segment_project_refuses_an_unfinalized_volume():
+    """Bone depth + slabs read the finalized volume: after pixels are added (plain ingest,
+    graph launch) and before the next finalize, segment_project returns USV_E_STATE; a
+    finalize (or a reset) makes it valid again."""
+    from paper_2412_00058_amd import UsvError, Graph, _lib, seg_params
+    say("case: segment_project on an unfinalized volume")
+    d = synth.cfg1()
+    vol = gpu_volume(d["grid"])
+    pid = add_probe(vol, d["probe"])
+    prm = seg_params(r=2, fallback_y=20, half=(2, 5))
+    V, S = vol.finalize()
+    vol.segment_project(prm, V, S)                  # a fresh volume: nothing to finalize
+    vol.ingest(pid, to_dev(d["frames"][:8]), d["poses"][:8])
+    with pytest.raises(UsvError) as e:
+        vol.segment_project(prm, V, S)
+    assert e.value.status == _lib.USV_E_STATE
+    V, S = vol.finalize()
+    dep, _, _ = vol.segment_project(prm, V, S)
+    gr = Graph(vol, pid)
+    gr.launch(d["frames"][8], d["poses"][8])
+    with pytest.raises(UsvError) as e:
+        vol.segment_project(prm, V, S)
+    assert e.value.status == _lib.USV_E_STATE
+    gr.close()
+    vol.reset()
+    vol.segment_project(prm, V, S)
+    vol.sync()
+    assert vol.status() == 0
+    vol.close()
