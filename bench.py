@@ -127,24 +127,17 @@ def time_oracle_splat(d5, n=128):
     return n / dt, dt
 
 
-def counters_record(src_hash, tile, bricks):
+def counters_record(src_hash, tile):
     """The committed rocprofv3 counter summary of the ingest kernel, if it was taken on the
-    current ingest kernel source with the same tile shape and brick shape; otherwise None."""
+    current ingest kernel source with the same tile shape; otherwise None."""
     p = os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json")
     try:
         rec = json.load(open(p))
     except (OSError, ValueError):
         return None
-    if rec.get("ingest_source_sha256") != src_hash or rec.get("tile") != list(tile) or \
-            rec.get("bricks") != list(bricks):
+    if rec.get("ingest_source_sha256") != src_hash or rec.get("tile") != list(tile):
         return None
     return rec
-
-
-def ingest_kernel_name(bricks):
-    """Name of the ingest kernel a plain call launches: the owner-computes kernel when the
-    probe has a brick shape, else the frame-major tiles."""
-    return "ingest_brick_kernel" if bricks[0] else "ingest_kernel"
 
 
 # device-scope atomic requests (64-byte segments per wave instruction) per second on the
@@ -171,7 +164,7 @@ def _per_kernel(csv_path, counter=None):
     return {k: {c: (sum(v.values()) / len(v), len(v)) for c, v in cs.items()} for k, cs in agg.items()}
 
 
-def counters_summary(fetch_csv, write_csv, out_json, atomic_csv=None, tile=None, bricks=(0, 0, 0)):
+def counters_summary(fetch_csv, write_csv, out_json, atomic_csv=None, tile=None):
     """Summarise two rocprofv3 --pmc runs of `bench.py --profile-pass` (FETCH_SIZE, then
     WRITE_SIZE; CSV output) into HBM bytes per ingest launch.  Each counter is scaled by
     what it reads for copy_u32_kernel, which the profile pass runs once on a buffer of
@@ -185,11 +178,9 @@ def counters_summary(fetch_csv, write_csv, out_json, atomic_csv=None, tile=None,
     write = {k: v["WRITE_SIZE"] for k, v in _per_kernel(write_csv, "WRITE_SIZE").items()}
     f_copy, w_copy = fetch["copy_u32_kernel"][0] * 1024.0, write["copy_u32_kernel"][0] * 1024.0
     kf, kw = copy_bytes / f_copy, copy_bytes / w_copy
-    kname = ingest_kernel_name(bricks)
-    f_ing, n_f = fetch[kname]
-    w_ing, n_w = write[kname]
+    f_ing, n_f = fetch["ingest_kernel"]
+    w_ing, n_w = write["ingest_kernel"]
     rec = {"ingest_source_sha256": ingest_source_hash(), "tile": list(tile) if tile else None,
-           "bricks": list(bricks), "kernel": kname,
            "fetch_kib_per_dispatch": round(f_ing, 1), "write_kib_per_dispatch": round(w_ing, 1),
            "dispatches": [n_f, n_w], "copy_bytes": copy_bytes,
            "copy_fetch_kib": round(f_copy / 1024.0, 1), "copy_write_kib": round(w_copy / 1024.0, 1),
@@ -197,7 +188,7 @@ def counters_summary(fetch_csv, write_csv, out_json, atomic_csv=None, tile=None,
            "hbm_bytes_per_launch": int(f_ing * 1024.0 * kf + w_ing * 1024.0 * kw)}
     if atomic_csv:
         atom = {k: v["TCC_EA0_ATOMIC_sum"] for k, v in _per_kernel(atomic_csv, "TCC_EA0_ATOMIC_sum").items()}
-        rec["atomic_requests_per_launch"] = int(atom[kname][0])
+        rec["atomic_requests_per_launch"] = int(atom["ingest_kernel"][0])
     for k in sorted(set(fetch) | set(write)):
         f = fetch.get(k, (0.0, 0))[0]
         w = write.get(k, (0.0, 0))[0]
@@ -254,12 +245,11 @@ def pmc_report(csv_paths, stats_csv, fetch_scale=2.0, write_scale=1.0):
 
 
 def ingest_source_hash():
-    """SHA-256 of what defines the ingest kernels: ingest.hip, bricks.hip and the ingest
-    section of usv_internal.h (from its start to the finalize section)."""
+    """SHA-256 of what defines the ingest kernel: ingest.hip and the ingest section of
+    usv_internal.h (from its start to the finalize section)."""
     csrc = os.path.join(ROOT, "paper_2412_00058_amd", "csrc")
     h = hashlib.sha256()
     h.update(open(os.path.join(csrc, "ingest.hip"), "rb").read())
-    h.update(open(os.path.join(csrc, "bricks.hip"), "rb").read())
     hdr = open(os.path.join(csrc, "usv_internal.h"), "rb").read()
     cut = hdr.find(b"// ---- finalize")
     h.update(hdr if cut < 0 else hdr[:cut])
@@ -672,16 +662,11 @@ def main():
     ap.add_argument("--cache5", default=None, help=".npz of the differentiable workload (written if missing)")
     ap.add_argument("--counters-tile", nargs=2, type=int, metavar=("W", "H"), default=None,
                     help="the ingest tile shape of the profiled pass (printed by it), stored with the summary")
-    ap.add_argument("--counters-bricks", nargs=3, type=int, metavar=("BX", "BY", "BZ"), default=(0, 0, 0),
-                    help="the brick shape of the profiled pass (printed by it; 0 0 0 = frame-major tiles)")
-    ap.add_argument("--force-bricks", nargs=3, type=int, metavar=("BX", "BY", "BZ"), default=None,
-                    help="override the autotuner's ingest layout: this brick shape (0 0 0 = frame-major tiles "
-                         "with the autotuned tile)")
     args = ap.parse_args()
     if args.counters_summary:
         dbs = args.counters_summary
         counters_summary(dbs[0], dbs[1], os.path.join(ROOT, "profiles", "ingest_cfg2_counters.json"),
-                         dbs[2] if len(dbs) > 2 else None, args.counters_tile, tuple(args.counters_bricks))
+                         dbs[2] if len(dbs) > 2 else None, args.counters_tile)
         return
     if args.pmc_report:
         print(pmc_report(args.pmc_report, args.stats))
@@ -760,10 +745,7 @@ def main():
     # then run the launches one after another with the same tile
     vol.set_ingest_overlap(not args.serial)
     vol.autotune(pid, frames[:1024], d["poses"][:1024], os.path.join(tempfile.gettempdir(), "usv_bench_tune.txt"))
-    if args.force_bricks is not None:
-        vol.set_bricks(pid, *args.force_bricks)
     tile = vol.tiling(pid)
-    bricks = vol.bricks(pid)
     frames_per_launch = vol.chunk(pid)
     overlap = not args.profile_pass and not args.serial
     vol.set_ingest_overlap(overlap)
@@ -847,14 +829,14 @@ def main():
             if i >= 2:
                 ev_ms.append(e0.elapsed_time(e1))
     value = F / (ms_step / 1e3)
-    print("[bench] %.3f ms/step  ingest %.3f  finalize %.3f  segment %.3f ms  tile %s  bricks %s  host submit "
-          "%.3f ms/step" % (ms_step, phase[0], phase[1], phase[2], tile, bricks, 1e3 * float(np.median(host_submit))),
-          file=sys.stderr, flush=True)
+    print("[bench] %.3f ms/step  ingest %.3f  finalize %.3f  segment %.3f ms  tile %s  host submit %.3f ms/step" %
+          (ms_step, phase[0], phase[1], phase[2], tile, 1e3 * float(np.median(host_submit))), file=sys.stderr,
+          flush=True)
     if args.profile_pass:
         # one plain copy of known size (the accumulator export) to calibrate byte counters
         snap = vol.export_accumulators()
         torch.cuda.synchronize()
-        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step, "tile": list(tile), "bricks": list(bricks),
+        print(json.dumps({"profile_pass": True, "ms_per_step": ms_step, "tile": list(tile),
                           "copy_bytes": snap.numel() * snap.element_size()}))
         return
 
@@ -886,7 +868,7 @@ def main():
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     hbm_floor_ms = bytes_launch / (HBM_PEAK_GBS * 1e9) * 1e3
     atomic_floor_ms = segs_launch / ATOMIC_REQ_RATE * 1e3
-    rec = counters_record(ingest_source_hash(), tile, bricks)
+    rec = counters_record(ingest_source_hash(), tile)
     traffic = rec.get("hbm_bytes_per_launch") if rec else None
     meas_req = rec.get("atomic_requests_per_launch") if rec else None
     # ALU floor: per kept pixel the method needs 3 FP32 adds (the per-column products and
@@ -906,10 +888,7 @@ def main():
         head = {"achieved": round(segs_launch / (per_launch_ms * 1e-3) / 1e9, 2), "peak": ATOMIC_REQ_RATE / 1e9,
                 "unit": "G requests/s"}
     roof = {"bound": bound, **head, "frac": round(floors[bound] / per_launch_ms, 4), "traffic": traffic,
-            "kernel": "%s (PNN scatter, %s, %d frames per launch)" % (
-                ingest_kernel_name(bricks),
-                "owner-computes bricks %dx%dx%d" % tuple(bricks) if bricks[0] else "frame-major tiles %dx%d" % tuple(tile),
-                frames_per_launch),
+            "kernel": "ingest_kernel (PNN scatter, %d frames per launch)" % frames_per_launch,
             "launch_ms": round(per_launch_ms, 5),
             "floors_ms": {k: round(v, 5) for k, v in floors.items()},
             "hbm": {"alg_bytes_per_launch": int(bytes_launch), "achieved_GBps": round(achieved, 1),
@@ -1030,7 +1009,7 @@ def main():
            "config": {"workload": "whole-spine sweep: 3600 frames 480x640 uint8 (0.1 mm px), 560 mm path with "
                                   "+-20 mm meander and +-5 deg jitter, grid 400x240x1120 @ 0.5 mm, calls of 64 "
                                   "frames, full finalize, ALG2 depth + slab projection h=2/5/10",
-                      "tile": list(tile), "bricks": list(bricks), "frames_per_launch": frames_per_launch,
+                      "tile": list(tile), "frames_per_launch": frames_per_launch,
                       "ingest_streams": 1 if args.serial else 2, "parallelism": "single GPU"},
            "breakdown_ms": {"ingest": round(phase[0], 4), "finalize": round(phase[1], 4),
                             "segment_project": round(phase[2], 4)},

@@ -324,9 +324,7 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
 
 /* Autotune the ingest tiling of a probe on sample data (n >= 1 frames) by timing
  * every candidate tile shape on a scratch copy of the grid, then 16 and 32 frames per
- * launch for the best shape, then the owner-computes brick shapes of
- * usv_probe_set_bricks (32x8x4, 32x8x8, 32x4x8, 32x16x4, 32x4x4, 16x8x4, 16x4x4, 16x8x8,
- * 16x16x4); the winners become the probe's tiling, launch size and brick shape.
+ * launch for the best shape; the winners become the probe's tiling and launch size.
  * Trials launch the way the volume currently does (serial, or overlapped after
  * usv_set_ingest_overlap), so set the mode first.  cache_path (nullable): results are
  * read from / appended to this text file, keyed by device, image size, pixel/voxel
@@ -345,23 +343,6 @@ usv_status usv_probe_chunk(const usv_volume *vol, int32_t probe_id, int32_t *fra
  * 120x64, 120x32, 240x16, 240x32, 240x8; anything else is USV_E_UNSUPPORTED.  Results
  * do not depend on the tiling (bit for bit), only the speed does. */
 usv_status usv_probe_set_tiling(usv_volume *vol, int32_t probe_id, int32_t tile_w, int32_t tile_h);
-
-/* Owner-computes layout of usv_ingest_frames for a probe (Sec. II.C, PNN distribution;
- * same result bit for bit, only the speed differs).  bx = 0 selects the frame-major
- * tiles (the default).  Otherwise each launch is split into voxel bricks of bx x by x bz
- * voxels (bx = 16 or 32, by and bz in [1, 64], bx by bz <= 4096) on a lattice anchored at
- * the grid origin; one block per brick of the launch's dirty box gathers the pixels of
- * every frame of the launch that can land in its brick and adds each of its voxels to the
- * accumulators once per launch, so a voxel crossed by many frames of a call costs one
- * global atomic instead of one per frame tile.  Frames of a call are grouped into
- * launches (at most the probe's frames per launch) so that a per-frame bound on the
- * pixels one voxel can receive sums to at most 4095 per launch; a frame whose bound alone
- * exceeds it takes the <= 4095-pixel frame-major tiles.  Other shapes:
- * USV_E_UNSUPPORTED.  usv_ingest_frames_cut, usv_ingest_batched and the graphs keep the
- * frame-major tiles. */
-usv_status usv_probe_set_bricks(usv_volume *vol, int32_t probe_id, int32_t bx, int32_t by, int32_t bz);
-/* The brick shape in use (bx = 0: frame-major tiles). */
-usv_status usv_probe_bricks(const usv_volume *vol, int32_t probe_id, int32_t *bx, int32_t *by, int32_t *bz);
 
 
 /* ---------------------------------------------------------------------------------

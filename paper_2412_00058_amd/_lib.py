@@ -17,8 +17,7 @@ EXPORTS = [
     "usv_export_accumulators", "usv_import_accumulators", "usv_destroy_volume", "usv_last_error",
     "usv_ingest_frames", "usv_ingest_frames_cut", "usv_set_ingest_overlap", "usv_join", "usv_cut_rows_alg1", "usv_cut_rows_alg2", "usv_vnn_create", "usv_vnn_reset", "usv_vnn_ingest",
     "usv_vnn_finalize", "usv_vnn_destroy", "usv_extract_slices", "usv_finalize", "usv_segment_project", "usv_segment_project_noalloc", "usv_ingest_batched", "usv_autotune",
-    "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_probe_set_bricks", "usv_probe_bricks",
-    "usv_graph_create", "usv_graph_launch",
+    "usv_probe_tiling", "usv_probe_chunk", "usv_probe_set_tiling", "usv_graph_create", "usv_graph_launch",
     "usv_graph_destroy", "usv_pipeline_create", "usv_pipeline_push", "usv_pipeline_flush", "usv_pipeline_stats",
     "usv_pipeline_destroy", "usv_splat_create", "usv_splat_destroy", "usv_splat_forward", "usv_overlap_loss",
     "usv_splat_backward", "usv_dw_clear", "usv_dw_ingest", "usv_dw_finalize", "usv_refine_motion", "usv_fold_pose", "usv_dirty_box", "usv_version",
@@ -114,8 +113,6 @@ def lib():
         "usv_probe_tiling": (I32, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
         "usv_probe_chunk": (I32, [P, I32, C.POINTER(I32)]),
         "usv_probe_set_tiling": (I32, [P, I32, I32, I32]),
-        "usv_probe_set_bricks": (I32, [P, I32, I32, I32, I32]),
-        "usv_probe_bricks": (I32, [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
         "usv_graph_create": (I32, [P, I32, PP]),
         "usv_graph_launch": (I32, [P, P, P, C.POINTER(Box)]),
         "usv_graph_destroy": (I32, [P]),

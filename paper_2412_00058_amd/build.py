@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libusv.so")
-SOURCES = ["runtime.hip", "ingest.hip", "bricks.hip", "finalize.hip", "segment.hip", "cut.hip", "vnn.hip", "export.hip", "fill.hip", "splat.hip", "pipeline.hip"]
+SOURCES = ["runtime.hip", "ingest.hip", "finalize.hip", "segment.hip", "cut.hip", "vnn.hip", "export.hip", "fill.hip", "splat.hip", "pipeline.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-fno-gpu-rdc", "-Wall", "-Wno-unused-function",

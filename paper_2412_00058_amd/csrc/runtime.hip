@@ -44,7 +44,6 @@ struct ProbeState {
   int chunk = kLaunchFrames;   // frames per ingest launch (autotuned, <= kLaunchFrames)
   Tiling t_safe{};   // <= 4095-pixel tiling, for frames that put > 2056 pixels in one voxel
   double mask_density = 1.0;
-  int bx = 0, by = 0, bz = 0;   // owner-computes brick of plain ingest calls (bx = 0: frame-major tiles)
 };
 
 struct StagingRing {
@@ -455,42 +454,6 @@ double max_pixels_per_voxel(const float M[9], int W, int H) {
   return side * side;
 }
 
-// Upper bound on the pixels of one frame that can land in one voxel, for the
-// owner-computes layout.  Two pixels p1, p2 in one voxel have |q_r(p1) - q_r(p2)| < 1 for
-// every axis r, so the linear part X_r = a_r du + b_r dv obeys |X_r| < 1 + 2E (E bounds the
-// FP32 evaluation error of q).  For two axes r, s with det = a_r b_s - a_s b_r != 0,
-// du = (b_s X_r - b_r X_s) / det and dv = (a_r X_s - a_s X_r) / det, so all pixels of the
-// voxel lie within a column range shorter than U = min (|b_r| + |b_s|)(1 + 2E) / |det| and
-// a row range shorter than V = min (|a_r| + |a_s|)(1 + 2E) / |det|: at most
-// (floor(U) + 1)(floor(V) + 1) pixels.  Infinity when no pair of axes is independent.
-double brick_pixels_per_voxel(const float M[9], int W, int H) {
-  const double a[3] = {M[0], M[3], M[6]}, b[3] = {M[1], M[4], M[7]};
-  double mag = 0.0;
-  for (int r = 0; r < 3; ++r)
-    mag = std::max(mag, std::fabs(a[r]) * W + std::fabs(b[r]) * H + std::fabs((double)M[3 * r + 2]));
-  const double t = (1.0 + 2.0 * 4.0 * mag * std::ldexp(1.0, -24)) * (1.0 + 1e-9);
-  double U = HUGE_VAL, V = HUGE_VAL;
-  for (int r = 0; r < 3; ++r)
-    for (int q = r + 1; q < 3; ++q) {
-      const double det = std::fabs(a[r] * b[q] - a[q] * b[r]);
-      if (!(det > 0.0)) continue;
-      U = std::min(U, (std::fabs(b[r]) + std::fabs(b[q])) * t / det);
-      V = std::min(V, (std::fabs(a[r]) + std::fabs(a[q])) * t / det);
-    }
-  if (!(U < 1e6) || !(V < 1e6)) return HUGE_VAL;
-  return (std::floor(U) + 1.0) * (std::floor(V) + 1.0);
-}
-
-struct BrickCand {
-  int bx, by, bz;
-};
-const BrickCand kBrickCands[] = {{32, 8, 4}, {32, 8, 8}, {32, 4, 8}, {32, 16, 4}, {32, 4, 4},
-                                 {16, 8, 4}, {16, 4, 4}, {16, 8, 8}, {16, 16, 4}};
-
-bool bricks_valid(int bx, int by, int bz) {
-  return (bx == 16 || bx == 32) && by >= 1 && by <= 64 && bz >= 1 && bz <= 64 && bx * by * bz <= kBrickWinMax;
-}
-
 // Fold + classify + dirty box for n poses.  Fills maps/fidx of the kept frames.
 // With rows_in ([n][2] inclusive row bands), frames keep only their band: empty bands
 // are skipped, the box covers the band, and the packed bands (lo | hi << 16) of the kept
@@ -564,95 +527,6 @@ usv_status launch_frames(usv_volume *v, const ProbeState &p, const uint8_t *fram
     ingest_launched(v);
   }
   return USV_OK;
-}
-
-// Owner-computes launches of the frames (maps, fidx): frames are taken in order into
-// launches of at most p.chunk frames whose pixels-per-voxel bounds sum to at most
-// kBrickMaxPerVoxel; each launch covers the bricks of its frames' dirty box.  Frames whose
-// bound alone exceeds it are returned in (rest_maps, rest_fidx) for the frame-major path.
-usv_status launch_frames_bricks(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
-                                int64_t frame_pitch, const std::vector<float> &maps, const std::vector<int32_t> &fidx,
-                                std::vector<float> &rest_maps, std::vector<int32_t> &rest_fidx) {
-  v->acc_quiet = false;
-  const int nk = (int)fidx.size();
-  const int dims[3] = {v->nx, v->ny, v->nz};
-  const int bs[3] = {p.bx, p.by, p.bz};
-  const int chunk = std::max(1, std::min(p.chunk, kLaunchFrames));
-  BrickLaunch a{};
-  a.d = make_desc(v, p, frames, row_pitch, frame_pitch);
-  a.bx = p.bx;
-  a.by = p.by;
-  a.bz = p.bz;
-  usv_box box = empty_box();
-  double load = 0.0;
-  auto flush = [&]() -> usv_status {
-    if (a.n_frames == 0) return USV_OK;
-    int64_t nb = 1;
-    int b0[3], nbk[3];
-    for (int r = 0; r < 3; ++r) {
-      b0[r] = box.lo[r] / bs[r];
-      nbk[r] = (box.hi[r] - 1) / bs[r] - b0[r] + 1;
-      nb *= nbk[r];
-    }
-    a.bx0 = b0[0];
-    a.by0 = b0[1];
-    a.bz0 = b0[2];
-    a.nbx = nbk[0];
-    a.nby = nbk[1];
-    a.nbz = nbk[2];
-    if (nb >= ((int64_t)1 << 31)) return fail(v, USV_E_UNSUPPORTED, "too many bricks in one launch");
-    a.n_bricks = (int32_t)nb;
-    hipStream_t s = ingest_stream(v);
-    if (v->overlap && !s) return check_hip(v, hipErrorUnknown, "ingest stream fork");
-    usv_status st = check_hip(v, launch_ingest_bricks(a, s), "ingest launch");
-    if (st != USV_OK) return st;
-    ingest_launched(v);
-    a.n_frames = 0;
-    box = empty_box();
-    load = 0.0;
-    return USV_OK;
-  };
-  for (int i = 0; i < nk; ++i) {
-    const float *M = &maps[(size_t)i * 9];
-    const double n_pv = brick_pixels_per_voxel(M, p.W, p.H);
-    int lo[3], hi[3];
-    if (!(n_pv <= kBrickMaxPerVoxel)) {
-      rest_maps.insert(rest_maps.end(), M, M + 9);
-      rest_fidx.push_back(fidx[(size_t)i]);
-      continue;
-    }
-    if (!frame_box(M, p.W, p.H, dims, lo, hi)) continue;
-    if (a.n_frames == chunk || load + n_pv > kBrickMaxPerVoxel) {
-      const usv_status st = flush();
-      if (st != USV_OK) return st;
-    }
-    a.fidx[a.n_frames] = fidx[(size_t)i];
-    for (int j = 0; j < 9; ++j) a.M[a.n_frames][j] = M[j];
-    ++a.n_frames;
-    load += n_pv;
-    box_union(box, lo, hi);
-  }
-  return flush();
-}
-
-// The launches of one plain ingest call: owner-computes bricks when the probe has a brick
-// shape (frames too dense for its LDS packing take the <= 4095-pixel tiles), else the
-// frame-major tiles (frames of the safe list on the <= 4095-pixel tiling).
-usv_status dispatch_frames(usv_volume *v, const ProbeState &p, const uint8_t *frames, int64_t row_pitch,
-                           int64_t frame_pitch, const std::vector<float> &maps, const std::vector<int32_t> &fidx,
-                           const std::vector<float> &smaps, const std::vector<int32_t> &sfidx) {
-  usv_status st;
-  if (p.bx > 0) {
-    std::vector<float> rmaps;
-    std::vector<int32_t> rfidx;
-    st = launch_frames_bricks(v, p, frames, row_pitch, frame_pitch, maps, fidx, rmaps, rfidx);
-    if (st == USV_OK) st = launch_frames_bricks(v, p, frames, row_pitch, frame_pitch, smaps, sfidx, rmaps, rfidx);
-    if (st != USV_OK || rfidx.empty()) return st;
-    return launch_frames(v, p, frames, row_pitch, frame_pitch, rmaps, rfidx, true);
-  }
-  st = launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx);
-  if (st != USV_OK || sfidx.empty()) return st;
-  return launch_frames(v, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
 }
 
 bool seg_params_ok(const usv_seg_params *pr, int32_t ny) {
@@ -1017,7 +891,9 @@ usv_status usv_ingest_frames(usv_volume *v, int32_t probe_id, const uint8_t *fra
   if (dirty_out) *dirty_out = box;
   touch(v, box);
   v->count_dirty = true;
-  return dispatch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx, smaps, sfidx);
+  st = launch_frames(v, p, frames, row_pitch, frame_pitch, maps, fidx);
+  if (st != USV_OK || sfidx.empty()) return st;
+  return launch_frames(v, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
 }
 
 usv_status usv_ingest_frames_cut(usv_volume *v, int32_t probe_id, const uint8_t *frames, int64_t row_pitch,
@@ -1166,29 +1042,6 @@ usv_status usv_probe_set_tiling(usv_volume *v, int32_t probe_id, int32_t tile_w,
     }
   }
   return fail(v, USV_E_UNSUPPORTED, "unsupported tile shape");
-}
-
-usv_status usv_probe_set_bricks(usv_volume *v, int32_t probe_id, int32_t bx, int32_t by, int32_t bz) {
-  if (!v || probe_id < 0 || probe_id >= (int32_t)v->probes.size()) return fail(v, USV_E_ARG, "unknown probe");
-  ProbeState &p = v->probes[(size_t)probe_id];
-  if (bx == 0) {
-    p.bx = p.by = p.bz = 0;
-    return USV_OK;
-  }
-  if (!bricks_valid(bx, by, bz)) return fail(v, USV_E_UNSUPPORTED, "unsupported brick shape");
-  p.bx = bx;
-  p.by = by;
-  p.bz = bz;
-  return USV_OK;
-}
-
-usv_status usv_probe_bricks(const usv_volume *v, int32_t probe_id, int32_t *bx, int32_t *by, int32_t *bz) {
-  if (!v || probe_id < 0 || probe_id >= (int32_t)v->probes.size() || !bx || !by || !bz) return USV_E_ARG;
-  const ProbeState &p = v->probes[(size_t)probe_id];
-  *bx = p.bx;
-  *by = p.by;
-  *bz = p.bz;
-  return USV_OK;
 }
 
 usv_status usv_fold_pose(const usv_grid_desc *grid, const usv_probe_desc *probe, const double *pose, float *M12) {
@@ -1423,20 +1276,16 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
     while (std::getline(in, line)) {
       std::istringstream ss(line);
       std::string k;
-      int lr = 0, kr = 0, chunk = kLaunchFrames, bx = 0, by = 0, bz = 0;
+      int lr = 0, kr = 0, chunk = kLaunchFrames;
       if (ss >> k >> lr >> kr && k == key) {
         float ms = 0.0f;
         if (!(ss >> chunk >> ms) || chunk < 1 || chunk > kLaunchFrames) chunk = kLaunchFrames;
-        if (!(ss >> bx >> by >> bz) || !bricks_valid(bx, by, bz)) bx = by = bz = 0;
         Tiling t = make_tiling(lr, kr, p.W, p.H);
         if (!tiling_valid(t)) break;
         const usv_status qs = quiesce(v);   // tile classes in use by queued launches
         if (qs != USV_OK) return qs;
         p.t = t;
         p.chunk = chunk;
-        p.bx = bx;
-        p.by = by;
-        p.bz = bz;
         return check_hip(v, upload_tile_class(p), "tile classes");
       }
     }
@@ -1478,21 +1327,18 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   Tiling best = keep;
   float best_ms = 1e30f;
   int best_chunk = kLaunchFrames;
-  int best_b[3] = {0, 0, 0};
-  // time one (tile shape, frames per launch, brick) setting on the scratch grid; < 0 if unusable
-  auto trial = [&](const Tiling &t, int chunk, const int *b) -> float {
+  // time one (tile shape, frames per launch) setting on the scratch grid; < 0 if unusable
+  auto trial = [&](const Tiling &t, int chunk) -> float {
     p.t = t;
     p.chunk = chunk;
-    p.bx = b[0];
-    p.by = b[1];
-    p.bz = b[2];
     if (upload_tile_class(p) != hipSuccess) return -1.0f;
     // the frame split depends on the candidate's LDS packing
     std::vector<float> maps, smaps;
     std::vector<int32_t> fidx, sfidx;
     if (prepare_frames(v, p, poses, n, maps, fidx, nullptr, &smaps, &sfidx) != USV_OK) return -1.0f;
     auto run = [&]() {
-      const usv_status r = dispatch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx, smaps, sfidx);
+      usv_status r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);
+      if (r == USV_OK && !sfidx.empty()) r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
       const usv_status j = join_side(&tmp);
       return r != USV_OK ? r : j;
     };
@@ -1510,32 +1356,21 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
     }
     return ms_best;
   };
-  // every tile shape with full launches, then fewer frames per launch for the best shape,
-  // then the owner-computes bricks (frames they cannot take use the best tile shape)
-  const int frame_major[3] = {0, 0, 0};
+  // every tile shape with full launches, then fewer frames per launch for the best shape
   for (const TileCand &c : kCands) {
     const Tiling t = make_tiling(c.lr, c.kr, p.W, p.H);
     if (!tiling_valid(t)) continue;
-    const float ms = trial(t, kLaunchFrames, frame_major);
+    const float ms = trial(t, kLaunchFrames);
     if (ms >= 0.0f && ms < best_ms) {
       best_ms = ms;
       best = t;
     }
   }
   for (int ch : {16, 32}) {
-    const float ms = trial(best, ch, frame_major);
+    const float ms = trial(best, ch);
     if (ms >= 0.0f && ms < best_ms) {
       best_ms = ms;
       best_chunk = ch;
-    }
-  }
-  for (const BrickCand &c : kBrickCands) {
-    const int b[3] = {c.bx, c.by, c.bz};
-    const float ms = trial(best, kLaunchFrames, b);
-    if (ms >= 0.0f && ms < best_ms) {
-      best_ms = ms;
-      best_chunk = kLaunchFrames;
-      for (int k = 0; k < 3; ++k) best_b[k] = b[k];
     }
   }
   (void)hipEventDestroy(e0);
@@ -1545,16 +1380,11 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   (void)hipFree(err);
   p.t = best;
   p.chunk = best_chunk;
-  p.bx = best_b[0];
-  p.by = best_b[1];
-  p.bz = best_b[2];
   st = check_hip(v, upload_tile_class(p), "tile classes");
   if (st != USV_OK) return st;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    if (out)
-      out << key << " " << best.lr << " " << best.kr << " " << best_chunk << " " << best_ms << " " << best_b[0] << " "
-          << best_b[1] << " " << best_b[2] << "\n";
+    if (out) out << key << " " << best.lr << " " << best.kr << " " << best_chunk << " " << best_ms << "\n";
   }
   return USV_OK;
 }

@@ -83,28 +83,8 @@ struct BatchLaunch {
   int64_t per_xcd;            // items per XCD (set by launch_ingest_batched)
 };
 
-// Owner-computes layout: one block per voxel brick (bx x by x bz voxels, bricks on a
-// lattice anchored at the grid origin) of the launch's dirty box; each block gathers the
-// pixels of every frame of the launch that can land in its brick and writes only its own
-// voxels.  The host groups frames so that the per-frame bounds on pixels per voxel sum
-// to at most kBrickMaxPerVoxel per launch (LDS words count << 20 | sum).
-constexpr int kBrickWinMax = 4096;        // LDS window entries of one brick block (16 KiB)
-constexpr int kBrickMaxPerVoxel = 4095;
-
-struct BrickLaunch {
-  SweepDesc d;
-  int32_t n_frames;
-  int32_t n_bricks;                // one block per brick, in order (z fastest, then y, then x)
-  int32_t bx, by, bz;              // brick size (bx 16 or 32)
-  int32_t bx0, by0, bz0;           // first brick of the box (in bricks)
-  int32_t nbx, nby, nbz;           // bricks of the box per axis
-  int32_t fidx[kLaunchFrames];
-  float M[kLaunchFrames][9];
-};
-
 // n_items = frames x tiles, one block per item
 hipError_t launch_ingest(const IngestLaunch &a, int n_items, hipStream_t s);
-hipError_t launch_ingest_bricks(const BrickLaunch &a, hipStream_t s);
 hipError_t launch_ingest_batched(const BatchLaunch &a, hipStream_t s);
 hipError_t launch_ingest_rows(const IngestLaunchRows &a, int n_items, hipStream_t s);
 hipError_t launch_ingest_devm(const SweepDesc &d, const float *M, const int32_t *fidx, int n_frames, hipStream_t s);

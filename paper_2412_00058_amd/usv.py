@@ -221,15 +221,6 @@ class Volume:
     def set_tiling(self, probe_id, tile_w, tile_h):
         check(lib().usv_probe_set_tiling(self.h, probe_id, int(tile_w), int(tile_h)), self.h)
 
-    def set_bricks(self, probe_id, bx, by=0, bz=0):
-        """Owner-computes brick (bx, by, bz) voxels for plain ingest calls; bx = 0: frame-major tiles."""
-        check(lib().usv_probe_set_bricks(self.h, probe_id, int(bx), int(by), int(bz)), self.h)
-
-    def bricks(self, probe_id):
-        x, y, z = C.c_int32(), C.c_int32(), C.c_int32()
-        check(lib().usv_probe_bricks(self.h, probe_id, C.byref(x), C.byref(y), C.byref(z)), self.h)
-        return x.value, y.value, z.value
-
     def ingest(self, probe_id, frames: torch.Tensor, poses) -> Box:
         """frames: uint8 device tensor [F, H, W] (row pitch = stride); poses [F, 4, 4] FP64 host."""
         _check_frames(frames, self._probe_hw.get(probe_id))
