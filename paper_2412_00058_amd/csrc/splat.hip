@@ -160,7 +160,9 @@ template <bool kU8>
 __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void *__restrict__ Iv, int64_t row_pitch,
                                                         int64_t frame_pitch, const double *__restrict__ Mq,
                                                         float *__restrict__ vols, int one_set, int win_cap) {
-  extern __shared__ __align__(16) unsigned long long win[];   // (S, W) of entry e at 2e, 2e + 1
+  // S of entry e at win[e], W at win[win_cap + e] (separate arrays: 8-byte strides keep the
+  // 64-bit LDS atomics of neighbouring lanes on different banks)
+  extern __shared__ __align__(16) unsigned long long win[];
   __shared__ float red[4];
   const int b = blockIdx.x;
   const int tc = b % g.tiles_x, rest = b / g.tiles_x;
@@ -198,7 +200,11 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
       val[j] = in ? static_cast<const float *>(Iv)[rowpix + u] : 0.0f;
     amax = fmaxf(amax, fabsf(val[j]));
   }
-  for (int e = threadIdx.x; e < 2 * we; e += 256) win[e] = 0ull;
+  unsigned long long *winW = win + win_cap;
+  for (int e = threadIdx.x; e < we; e += 256) {
+    win[e] = 0ull;
+    winW[e] = 0ull;
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
@@ -239,8 +245,8 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
       for (int dlt = 0; dlt < 8; ++dlt) {
         if (!(okm & (1u << dlt))) continue;
         const int e = (c0 + (dlt & 1) - lo[0]) + wx * ((c1 + ((dlt >> 1) & 1) - lo[1]) + wy * (c2 + (dlt >> 2) - lo[2]));
-        atomicAdd(&win[2 * e], (unsigned long long)aS[dlt]);
-        atomicAdd(&win[2 * e + 1], (unsigned long long)aW[dlt]);
+        atomicAdd(&win[e], (unsigned long long)aS[dlt]);
+        atomicAdd(&winW[e], (unsigned long long)aW[dlt]);
       }
     };
 #pragma unroll
@@ -266,11 +272,15 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
           aW[dlt] = 0;
         }
       }
+      // w = wx wy wz with the (y, z) products shared; sc_s and sc_w are powers of two, so
+      // w (val sc_s) and w sc_w round exactly as (w val) sc_s and w sc_w would
+      const float gx0 = 1.0f - p.f[0], gy0 = 1.0f - p.f[1], gz0 = 1.0f - p.f[2];
+      const float wyz[4] = {gy0 * gz0, p.f[1] * gz0, gy0 * p.f[2], p.f[1] * p.f[2]};
+      const float vs = val[j] * sc_s;
 #pragma unroll
       for (int dlt = 0; dlt < 8; ++dlt) {
-        const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
-        const float w = (bx ? p.f[0] : 1.0f - p.f[0]) * (by ? p.f[1] : 1.0f - p.f[1]) * (bz ? p.f[2] : 1.0f - p.f[2]);
-        aS[dlt] += (long long)__float2int_rn((w * val[j]) * sc_s);
+        const float w = (dlt & 1 ? p.f[0] : gx0) * wyz[dlt >> 1];
+        aS[dlt] += (long long)__float2int_rn(w * vs);
         aW[dlt] += (long long)__float2int_rn(w * sc_w);
       }
     }
@@ -281,7 +291,7 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
   const double inv_s = ldexp(1.0, -ks), inv_w = ldexp(1.0, -30);
   const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
   for (int e = threadIdx.x; e < we; e += 256) {
-    const ulonglong2 sw = *reinterpret_cast<const ulonglong2 *>(&win[2 * e]);
+    const ulonglong2 sw = make_ulonglong2(win[e], winW[e]);
     if (sw.x == 0ull && sw.y == 0ull) continue;
     const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
     const int ix = e - r1 * wx;
@@ -336,6 +346,29 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restr
   if (threadIdx.x == 0) out[0] = t;
 }
 
+// Trilinear interpolation of corner values c[d], d = bx + 2 by + 4 bz, at fractions
+// (fx, fy, fz): seven lerps (each (1 - t) a + t b = a + t (b - a)).
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+__device__ __forceinline__ float trilerp(const float c[8], float fx, float fy, float fz) {
+  const float y0 = lerpf(lerpf(c[0], c[1], fx), lerpf(c[2], c[3], fx), fy);
+  const float y1 = lerpf(lerpf(c[4], c[5], fx), lerpf(c[6], c[7], fx), fy);
+  return lerpf(y0, y1, fz);
+}
+
+// Gradient of the trilinear interpolant of c with respect to (fx, fy, fz):
+// d/dfx = the (y, z) bilinear interpolation of the x differences, d/dfy = the z lerp of
+// the y differences of the x lerps, d/dfz = the difference of the two xy bilinear values.
+__device__ __forceinline__ void trigrad(const float c[8], float fx, float fy, float fz, float g[3]) {
+  const float dx00 = c[1] - c[0], dx10 = c[3] - c[2], dx01 = c[5] - c[4], dx11 = c[7] - c[6];
+  g[0] = lerpf(lerpf(dx00, dx10, fy), lerpf(dx01, dx11, fy), fz);
+  const float x00 = fmaf(fx, dx00, c[0]), x10 = fmaf(fx, dx10, c[2]);
+  const float x01 = fmaf(fx, dx01, c[4]), x11 = fmaf(fx, dx11, c[6]);
+  const float dy0 = x10 - x00, dy1 = x11 - x01;
+  g[1] = lerpf(dy0, dy1, fz);
+  g[2] = fmaf(fy, dy1, x01) - fmaf(fy, dy0, x00);
+}
+
 // Backward of one 32x32 pixel tile.  The tile's voxel window of the frame set's two
 // gradient volumes (dL/dS, dL/dW) is staged in LDS with coalesced row loads, so the 8
 // corner gathers of each pixel are LDS reads; windows too large for LDS gather from
@@ -368,6 +401,7 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
   const int64_t we64 = any ? (int64_t)wx * wy * wz : 0;
   const bool staged = any && we64 <= kSplatWin;
+  const int wxy = wx * wy;
   // this thread's pixel values (rows ty0, ty0 + 8, ...), loaded first so that they arrive
   // while the window is staged
   const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;
@@ -408,22 +442,16 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   float acc[6] = {0, 0, 0, 0, 0, 0};
   // dI of one pixel and its terms of the pose gradient, from its 8 corner values
   // (corners outside the grid contribute nothing)
+  // dI of one pixel and its terms of the pose gradient from its 8 corner values (zero
+  // for corners outside the grid, which contribute nothing): dI = the trilinear
+  // interpolation of dL/dS, dL/dq = the gradient of the interpolation of
+  // coef = I dL/dS + dL/dW
   auto accumulate = [&](const PixW &p, const double *pd, float val, const float *gs, const float *gw, int64_t pix) {
-    float di = 0.0f, gq[3] = {0.0f, 0.0f, 0.0f};
+    float coef[8], gq[3];
 #pragma unroll
-    for (int dlt = 0; dlt < 8; ++dlt) {
-      const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
-      if (!(bx ? p.ok1[0] : p.ok0[0]) || !(by ? p.ok1[1] : p.ok0[1]) || !(bz ? p.ok1[2] : p.ok0[2])) continue;
-      const float fx = bx ? p.f[0] : 1.0f - p.f[0];
-      const float fy = by ? p.f[1] : 1.0f - p.f[1];
-      const float fz = bz ? p.f[2] : 1.0f - p.f[2];
-      di += fx * fy * fz * gs[dlt];
-      const float coef = val * gs[dlt] + gw[dlt];
-      gq[0] += coef * (bx ? 1.0f : -1.0f) * fy * fz;
-      gq[1] += coef * (by ? 1.0f : -1.0f) * fx * fz;
-      gq[2] += coef * (bz ? 1.0f : -1.0f) * fx * fy;
-    }
-    if (dI) dI[pix] = di;
+    for (int dlt = 0; dlt < 8; ++dlt) coef[dlt] = fmaf(val, gs[dlt], gw[dlt]);
+    if (dI) dI[pix] = trilerp(gs, p.f[0], p.f[1], p.f[2]);
+    trigrad(coef, p.f[0], p.f[1], p.f[2], gq);
     const float rx = (float)(pd[0] - pc[0]), ry = (float)(pd[1] - pc[1]), rz = (float)(pd[2] - pc[2]);
     acc[0] += gq[0];
     acc[1] += gq[1];
@@ -445,16 +473,15 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
         const int v = v0 + ty0 + 8 * (k2 + h);
         const bool in = u <= u1 && v <= v1;
         pixel_coord(m, u, v, g, p[h], pd[h]);
+        const int base = (p[h].i0[0] - lo[0]) + wx * ((p[h].i0[1] - lo[1]) + wy * (p[h].i0[2] - lo[2]));
 #pragma unroll
         for (int dlt = 0; dlt < 8; ++dlt) {
           const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
           const bool ok = in && (bx ? p[h].ok1[0] : p[h].ok0[0]) && (by ? p[h].ok1[1] : p[h].ok0[1]) &&
                           (bz ? p[h].ok1[2] : p[h].ok0[2]);
-          const int cx = p[h].i0[0] + bx, cy = p[h].i0[1] + by, cz = p[h].i0[2] + bz;
-          const int idx = ok ? (cx - lo[0]) + wx * ((cy - lo[1]) + wy * (cz - lo[2])) : 0;
-          const float2 t = gwin[idx];
-          gs[h][dlt] = t.x;
-          gw[h][dlt] = t.y;
+          const float2 t = gwin[ok ? base + bx + by * wx + bz * wxy : 0];
+          gs[h][dlt] = ok ? t.x : 0.0f;
+          gw[h][dlt] = ok ? t.y : 0.0f;
         }
       }
 #pragma unroll
@@ -480,8 +507,8 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
         const int64_t gi = ok ? (int64_t)(p.i0[0] + bx) +
                                     (int64_t)g.nx * ((int64_t)(p.i0[1] + by) + (int64_t)g.ny * (p.i0[2] + bz))
                               : 0;
-        gs[dlt] = GS[gi];
-        gw[dlt] = GW[gi];
+        gs[dlt] = ok ? GS[gi] : 0.0f;
+        gw[dlt] = ok ? GW[gi] : 0.0f;
       }
       accumulate(p, pd, vals[kr], gs, gw, ((int64_t)f * g.H + v) * g.W + u);
     }
