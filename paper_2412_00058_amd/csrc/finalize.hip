@@ -48,25 +48,49 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t den) {
   return q;
 }
 
-// round-half-up(s / c) = floor(s / c + 1/2) for 1 <= c <= 2048 and s <= 255 c, in FP32:
-// s is exact (< 2^19), rcp is within 1 ulp, so fl(s rcp(c)) is within 4.6e-5 of s / c
-// and adding 0.5001 (rounding error < 1.6e-5 below 256.5) lands within [+3.9e-5,
-// +1.7e-4] of s / c + 1/2, whose fractional part is a multiple of 1 / (2c) >= 2.4e-4
-// below 1: the truncation is the floor.  Outside that range (c = 0, s > 255 c, c > 2048)
+// Reciprocals of the counts 1 .. kRcpTab - 1 (entry 0 holds 1), one table per block in
+// LDS: the hardware reciprocal is a quarter-rate instruction, and every voxel needs one
+// for its mean and one for its fill.
+constexpr int kRcpTab = 2048;
+
+// min(round-half-up(s / c), 255) for 1 <= c < 2048, r = rcp(c) (within 1 ulp): for
+// s <= 255 c, s is exact (< 2^19) and the single rounding of the fused s r + 0.5001 lands
+// within [+5.5e-5, +1.5e-4] of s / c + 1/2, whose fractional part is a multiple of
+// 1 / (2c) >= 2.4e-4 below 1, so the truncation is the floor; for s > 255 c the value
+// is at least 255 and the cap gives 255.  (Checked exhaustively on the CPU.)  For c = 0
 // the result is bounded and unused: the callers select another value.
-__device__ __forceinline__ uint32_t round_mean_small(uint32_t s, uint32_t c) {
-  const float q = (float)s * __builtin_amdgcn_rcpf((float)(c ? c : 1u)) + 0.5001f;
-  return (uint32_t)fminf(q, 65535.0f);
+__device__ __forceinline__ uint32_t mean_capped(uint32_t s, float r) {
+  return (uint32_t)fminf(fmaf((float)s, r, 0.5001f), 255.0f);
 }
 
-// LDS word of raw (s, c): 0 if c = 0, else round-half-up(s / c) | 1 << 16, capped at
-// 255 (s > 255 c only in imported data).  Selects instead of branches, except for the
-// rare counts above 2048, which take the integer division.
-__device__ __forceinline__ uint32_t normalise(uint32_t s, uint32_t c) {
-  uint32_t q = round_mean_small(s, c);
-  if (c > 2048u) q = udiv_small(2u * s + c, 2u * c);
-  q = s > 255u * c ? 255u : q;   // also covers garbage from c = 0 or a huge s
-  return c ? (q | (1u << 16)) : 0u;
+// LDS word of raw (s, c) with c >= 2048: the integer division (s > 255 c only in
+// imported data, capped).
+__device__ __forceinline__ uint32_t normalise_big(uint32_t s, uint32_t c) {
+  uint32_t q = udiv_small(2u * s + c, 2u * c);
+  q = s > 255u * c ? 255u : q;
+  return q | (1u << 16);
+}
+
+// LDS words of four raw (s, c) (counts packed two per word): 0 if c = 0, else the
+// capped mean | 1 << 16.  One test per four voxels sends the rare counts >= 2048 to the
+// integer division.
+__device__ __forceinline__ uint4 normalise4(const uint32_t s[4], uint32_t cw0, uint32_t cw1, const float *rtab) {
+  const uint32_t c[4] = {cw0 & 0xFFFFu, cw0 >> 16, cw1 & 0xFFFFu, cw1 >> 16};
+  uint32_t w[4];
+  if (((cw0 | cw1) & 0xF800F800u) == 0u) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w[e] = c[e] ? (mean_capped(s[e], rtab[c[e]]) | (1u << 16)) : 0u;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      w[e] = c[e] == 0u ? 0u : (c[e] < (uint32_t)kRcpTab ? (mean_capped(s[e], rtab[c[e]]) | (1u << 16))
+                                                          : normalise_big(s[e], c[e]));
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ uint32_t normalise1(uint32_t s, uint32_t c, const float *rtab) {
+  return c == 0u ? 0u : (c < (uint32_t)kRcpTab ? (mean_capped(s, rtab[c]) | (1u << 16)) : normalise_big(s, c));
 }
 
 // Raw accumulator words of one plane for this thread: up to kPPT pieces of four voxels
@@ -82,7 +106,9 @@ struct Raw {
 template <bool kVec>
 __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
   __shared__ __align__(16) uint32_t plane[3][PLANE];
+  __shared__ float rtab[kRcpTab];
   const int tid = threadIdx.x;
+  for (int i = tid; i < kRcpTab; i += 256) rtab[i] = __builtin_amdgcn_rcpf((float)(i ? i : 1));
   // XCD-aware block order: the hardware deals blocks to the 8 XCDs in turn, so block L
   // runs on XCD L % 8.  Each XCD gets a contiguous range of (y, z) bands and runs all x
   // blocks of a band back to back, so the cache lines that neighbouring blocks share
@@ -166,11 +192,9 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
 #pragma unroll
     for (int i = 0; i < kPPT; ++i) {
       if (tid + 256 * i >= kPieces) break;
-      *reinterpret_cast<uint4 *>(p + plds[i]) =
-          make_uint4(normalise(r.s[i][0], r.c[i][0] & 0xFFFFu), normalise(r.s[i][1], r.c[i][0] >> 16),
-                     normalise(r.s[i][2], r.c[i][1] & 0xFFFFu), normalise(r.s[i][3], r.c[i][1] >> 16));
+      *reinterpret_cast<uint4 *>(p + plds[i]) = normalise4(r.s[i], r.c[i][0], r.c[i][1], rtab);
     }
-    if (edge) p[elds] = normalise(r.es, r.ec);
+    if (edge) p[elds] = normalise1(r.es, r.ec, rtab);
   };
   // in-plane 3x3 sums of this thread's six voxels
   auto psum = [&](int slot, uint32_t *P) {
@@ -189,6 +213,7 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
   // planes ahead; plane z + 1 goes to buffer (z - zs + 2) mod 3
 #pragma unroll
   for (int d = 0; d < kDepth; ++d) load(zs - 1 + d, q[d]);
+  __syncthreads();   // the reciprocal table
   store(0, q[0]);
   load(zs - 1 + kDepth, q[0]);
   __syncthreads();
@@ -229,7 +254,7 @@ __global__ __launch_bounds__(256, 4) void finalize_kernel(FinalizeArgs a) {
       const uint32_t nb = Pm[k] + P0[k] + Pp[k];
       const uint32_t n = nb >> 16, sv = nb & 0xFFFFu;
       const bool meas = (c0 >> 16) != 0u, fill = n >= fmin;
-      const uint32_t vf = round_mean_small(sv, n);   // n <= 26, sv <= 255 n (garbage if n = 0)
+      const uint32_t vf = mean_capped(sv, rtab[n]);   // n <= 26, sv <= 255 n (garbage if n = 0)
       const uint32_t V = meas ? (c0 & 0xFFu) : (fill ? vf : 0u);
       const uint32_t st = meas ? 1u : (fill ? 2u : 0u);
       __builtin_amdgcn_raw_buffer_store_b8((uint8_t)V, rV, (int)i, 0, 0);
