@@ -177,7 +177,7 @@ usv_status usv_ingest_frames(usv_volume *vol, int32_t probe_id, const uint8_t *f
 /* Overlapped ingest (off by default).  Consecutive ingest launches of one volume are
  * independent (integer atomics commute), but launches on one stream run back to back,
  * each leaving the GPU partly idle at its start and end.  With overlap on, ingest
- * launches alternate between two library streams (default priority).  A burst of
+ * launches rotate over three library streams (default priority).  A burst of
  * ingest calls starts at the first ingest call after a join: the side streams then wait
  * for everything enqueued on the volume's stream so far, and later calls of the burst
  * add no waits (no host synchronisation calls per launch), so work the caller enqueues

@@ -27,6 +27,8 @@ using namespace usv;
 namespace {
 
 constexpr int kMaxProbes = 16;
+// library streams that consecutive ingest launches alternate between (overlapped ingest)
+constexpr int kSides = 3;
 constexpr int64_t kMaxVox = (int64_t)1 << 31;
 constexpr double kMapLimit = 18446744073709551616.0;  // 2^64
 
@@ -84,8 +86,8 @@ struct usv_volume {
   // overlapped ingest (usv_set_ingest_overlap): launches alternate between two library
   // streams that wait for `stream` at each launch; `stream` waits for them lazily
   bool overlap = false;
-  hipStream_t side[2] = {nullptr, nullptr};
-  hipEvent_t side_ev[2] = {nullptr, nullptr};
+  hipStream_t side[kSides] = {};
+  hipEvent_t side_ev[kSides] = {};
   hipEvent_t main_ev = nullptr;
   int next_side = 0;
   bool side_pending = false;   // the side streams hold work `stream` has not waited for
@@ -94,11 +96,11 @@ struct usv_volume {
   // its last read of the accumulators; a reset that follows with nothing touching the
   // accumulators in between zeroes them on side stream 0 after acc_ev, so calls that do
   // not touch them (segment_project) run beside the zeroing.  zero_ev marks its end for
-  // side stream 1.
+  // the other side streams.
   hipEvent_t acc_ev = nullptr, zero_ev = nullptr;
   bool acc_quiet = false;      // nothing has touched the accumulators since acc_ev
   bool unfinalized = false;    // pixels added (or accumulators imported) since the last finalize / reset
-  bool zero_pending = false;   // side stream 1 has not yet waited for zero_ev
+  bool zero_pending = false;   // side streams 1 .. kSides - 1 have not yet waited for zero_ev
 };
 
 struct usv_graph {
@@ -153,7 +155,7 @@ usv_status check_hip(usv_volume *v, hipError_t e, const char *what) {
 usv_status join_side(usv_volume *v, bool touches_acc = true) {
   if (touches_acc) v->acc_quiet = false;
   if (!v->side_pending) return USV_OK;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kSides; ++k) {
     usv_status st = check_hip(v, hipEventRecord(v->side_ev[k], v->side[k]), "join ingest streams");
     if (st == USV_OK) st = check_hip(v, hipStreamWaitEvent(v->stream, v->side_ev[k], 0), "join ingest streams");
     if (st != USV_OK) return st;
@@ -178,12 +180,12 @@ usv_status quiesce(usv_volume *v) {
 hipStream_t ingest_stream(usv_volume *v) {
   if (!v->overlap) return v->stream;
   if (!v->burst) {
-    if (hipEventRecord(v->main_ev, v->stream) != hipSuccess ||
-        hipStreamWaitEvent(v->side[0], v->main_ev, 0) != hipSuccess ||
-        hipStreamWaitEvent(v->side[1], v->main_ev, 0) != hipSuccess)
-      return nullptr;
+    if (hipEventRecord(v->main_ev, v->stream) != hipSuccess) return nullptr;
+    for (int k = 0; k < kSides; ++k)
+      if (hipStreamWaitEvent(v->side[k], v->main_ev, 0) != hipSuccess) return nullptr;
     // a zeroing queued on side stream 0 by a reset precedes every launch of the burst
-    if (v->zero_pending && hipStreamWaitEvent(v->side[1], v->zero_ev, 0) != hipSuccess) return nullptr;
+    for (int k = 1; k < kSides && v->zero_pending; ++k)
+      if (hipStreamWaitEvent(v->side[k], v->zero_ev, 0) != hipSuccess) return nullptr;
     v->zero_pending = false;
     v->burst = true;
     v->side_pending = true;
@@ -193,7 +195,7 @@ hipStream_t ingest_stream(usv_volume *v) {
 
 // After a launch on ingest_stream(v): the next launch goes to the other side stream.
 void ingest_launched(usv_volume *v) {
-  if (v->overlap) v->next_side ^= 1;
+  if (v->overlap) v->next_side = v->next_side + 1 == kSides ? 0 : v->next_side + 1;
 }
 
 bool finite_all(const double *p, int n) {
@@ -817,7 +819,7 @@ usv_status usv_import_accumulators(usv_volume *v, const void *src) {
 usv_status usv_destroy_volume(usv_volume *v) {
   if (!v) return USV_E_ARG;
   (void)hipStreamSynchronize(v->stream);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kSides; ++k) {
     if (v->side[k]) {
       (void)hipStreamSynchronize(v->side[k]);
       (void)hipStreamDestroy(v->side[k]);
@@ -853,7 +855,7 @@ usv_status usv_set_ingest_overlap(usv_volume *v, int32_t enable) {
     return st;
   }
   if (!v->side[0]) {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kSides; ++k) {
       if (hipStreamCreateWithFlags(&v->side[k], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&v->side_ev[k], hipEventDisableTiming) != hipSuccess)
         return check_hip(v, hipErrorUnknown, "ingest streams");
@@ -1144,7 +1146,7 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
     if (!v || !v->side_pending) continue;
     if (join_side(v) != USV_OK) return USV_E_DEVICE;   // records the side events
     if (v != owner)
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < kSides; ++k)
         if (hipStreamWaitEvent(owner->stream, v->side_ev[k], 0) != hipSuccess) return USV_E_DEVICE;
   }
   // entry 2i: ordinary frames of sweep i; 2i+1: frames that need the small-tile tiling
@@ -1315,7 +1317,7 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
   // trials launch the way the volume will: with overlap on, on the volume's side streams
   // (shared handles, joined after each trial run)
   tmp.overlap = v->overlap;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kSides; ++k) {
     tmp.side[k] = v->side[k];
     tmp.side_ev[k] = v->side_ev[k];
   }
