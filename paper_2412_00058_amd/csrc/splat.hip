@@ -18,6 +18,7 @@
 //   dw_finalize_kernel   : the distance-weighted (tent kernel) compounding's S / W.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "usv_internal.h"
 
@@ -26,7 +27,7 @@ namespace usv {
 namespace {
 
 constexpr int STW = 32, STH = 32;
-constexpr int kSplatWin = 2816;   // (S, W) fixed-point pairs per block: 44 KiB
+constexpr int kSplatWin = 2816;   // window entries per block (forward: two arrays of 32- or 64-bit words; backward: float2)
 
 __device__ void mat3_mul(const double *a, const double *b, double *c) {
   for (int i = 0; i < 3; ++i)
@@ -148,21 +149,26 @@ __device__ __forceinline__ void pixel_coord(const double *m, int u, int v, const
   }
 }
 
-// Forward splat of one 32x32 pixel tile.  Contributions are merged in an LDS window as
-// 64-bit fixed-point integers (integer LDS atomics are several times faster than FP32
-// ones on gfx950): each term is rounded to a 32-bit integer -- W in 2^-30 units, S in
-// 2^-(30 - e) units where 2^e bounds |I| over the tile -- so a term converts with one
-// instruction and no window sum can reach 2^41; each term is rounded by at most 2^-31 of
-// its bound.  The window (dynamic LDS, win_cap entries, sized by the host from the
-// tile's largest possible voxel box) is flushed with FP32 global atomics of the
-// converted sums.
+// Forward splat of one 32x32 pixel tile.  Contributions are merged in an LDS window of
+// fixed-point integers (integer LDS atomics are several times faster than FP32 ones on
+// gfx950): each term is rounded to an integer -- W in 2^-kw units, S in 2^-(kw - e) units
+// where 2^e bounds |I| over the tile -- so a term converts with one instruction and is at
+// most 2^kw in magnitude; each term is rounded by at most 2^-(kw+1) of its bound.  The
+// splat (FP32 intensities) keeps 32-bit words: the host picks kw so that the terms one
+// voxel can receive from one frame (at most term_max, below) sum to less than 2^31.  The
+// distance-weighted compounding (uint8 frames, kU8), whose volume S / W amplifies the
+// rounding where the weight is small, keeps 64-bit words with kw = 30 (no window sum
+// reaches 2^41).  The window (dynamic LDS, win_cap entries of S and of W, sized by the
+// host from the tile's largest possible voxel box) is flushed with FP32 global atomics of
+// the converted sums.
 template <bool kU8>
 __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void *__restrict__ Iv, int64_t row_pitch,
                                                         int64_t frame_pitch, const double *__restrict__ Mq,
-                                                        float *__restrict__ vols, int one_set, int win_cap) {
-  // S of entry e at win[e], W at win[win_cap + e] (separate arrays: 8-byte strides keep the
-  // 64-bit LDS atomics of neighbouring lanes on different banks)
-  extern __shared__ __align__(16) unsigned long long win[];
+                                                        float *__restrict__ vols, int one_set, int win_cap, int kw) {
+  using Acc = typename std::conditional<kU8, long long, int>::type;
+  // S of entry e at win[e], W at win[win_cap + e]
+  extern __shared__ __align__(16) unsigned char win_raw[];
+  Acc *win = reinterpret_cast<Acc *>(win_raw);
   __shared__ float red[4];
   const int b = blockIdx.x;
   const int tc = b % g.tiles_x, rest = b / g.tiles_x;
@@ -200,10 +206,10 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
       val[j] = in ? static_cast<const float *>(Iv)[rowpix + u] : 0.0f;
     amax = fmaxf(amax, fabsf(val[j]));
   }
-  unsigned long long *winW = win + win_cap;
+  Acc *winW = win + win_cap;
   for (int e = threadIdx.x; e < we; e += 256) {
-    win[e] = 0ull;
-    winW[e] = 0ull;
+    win[e] = 0;
+    winW[e] = 0;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
@@ -212,8 +218,8 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
   amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   int ex = 0;
   if (amax > 0.0f && amax <= 3.0e38f) (void)frexpf(amax, &ex);   // |I| < 2^ex
-  const int ks = min(127, max(-126, 30 - ex));   // scale exponent of S (a normal float)
-  const float sc_s = ldexpf(1.0f, ks), sc_w = ldexpf(1.0f, 30);
+  const int ks = min(127, max(-126, kw - ex));   // scale exponent of S (a normal float)
+  const float sc_s = ldexpf(1.0f, ks), sc_w = ldexpf(1.0f, kw);
   if (direct) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
     // consecutive pixels of the run that share their base voxel add their fixed-point
     // terms in registers (integer sums: the same totals as one LDS atomic per term) and
     // reach the window once per base voxel
-    long long aS[8], aW[8];
+    Acc aS[8], aW[8];
     int c0 = 0, c1 = 0, c2 = 0;
     uint32_t okm = 0u;   // bit d: corner d inside the grid
     bool open = false;
@@ -245,8 +251,13 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
       for (int dlt = 0; dlt < 8; ++dlt) {
         if (!(okm & (1u << dlt))) continue;
         const int e = (c0 + (dlt & 1) - lo[0]) + wx * ((c1 + ((dlt >> 1) & 1) - lo[1]) + wy * (c2 + (dlt >> 2) - lo[2]));
-        atomicAdd(&win[e], (unsigned long long)aS[dlt]);
-        atomicAdd(&winW[e], (unsigned long long)aW[dlt]);
+        if (kU8) {
+          atomicAdd(reinterpret_cast<unsigned long long *>(&win[e]), (unsigned long long)aS[dlt]);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&winW[e]), (unsigned long long)aW[dlt]);
+        } else {
+          atomicAdd(reinterpret_cast<int *>(&win[e]), (int)aS[dlt]);
+          atomicAdd(reinterpret_cast<int *>(&winW[e]), (int)aW[dlt]);
+        }
       }
     };
 #pragma unroll
@@ -280,26 +291,28 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
 #pragma unroll
       for (int dlt = 0; dlt < 8; ++dlt) {
         const float w = (dlt & 1 ? p.f[0] : gx0) * wyz[dlt >> 1];
-        aS[dlt] += (long long)__float2int_rn(w * vs);
-        aW[dlt] += (long long)__float2int_rn(w * sc_w);
+        aS[dlt] += (Acc)__float2int_rn(w * vs);
+        aW[dlt] += (Acc)__float2int_rn(w * sc_w);
       }
     }
     if (open) flush();
   }
   __syncthreads();
   if (direct) return;
-  const double inv_s = ldexp(1.0, -ks), inv_w = ldexp(1.0, -30);
+  const double inv_s = ldexp(1.0, -ks), inv_w = ldexp(1.0, -kw);
   const uint32_t mag_wx = 0xFFFFFFFFu / (uint32_t)wx + 1u, mag_wy = 0xFFFFFFFFu / (uint32_t)wy + 1u;
   for (int e = threadIdx.x; e < we; e += 256) {
-    const ulonglong2 sw = make_ulonglong2(win[e], winW[e]);
-    if (sw.x == 0ull && sw.y == 0ull) continue;
+    const Acc ws = win[e], ww = winW[e];
+    if ((ws | ww) == 0) continue;
     const int r1 = wx == 1 ? e : (int)__umulhi((uint32_t)e, mag_wx);
     const int ix = e - r1 * wx;
     const int ez = wy == 1 ? r1 : (int)__umulhi((uint32_t)r1, mag_wy);
     const int ey = r1 - ez * wy;
     const int64_t gi = (int64_t)(lo[0] + ix) + (int64_t)g.nx * ((int64_t)(lo[1] + ey) + (int64_t)g.ny * (lo[2] + ez));
-    atomicAdd(S + gi, (float)((double)(long long)sw.x * inv_s));
-    atomicAdd(Wt + gi, (float)((double)(long long)sw.y * inv_w));
+    // 32-bit words: one rounding of the integer, the power-of-two scale is exact; 64-bit
+    // words: exact in FP64, one rounding to FP32
+    atomicAdd(S + gi, kU8 ? (float)((double)ws * inv_s) : (float)ws * (float)inv_s);
+    atomicAdd(Wt + gi, kU8 ? (float)((double)ww * inv_w) : (float)ww * (float)inv_w);
   }
 }
 
@@ -642,6 +655,27 @@ __global__ void dw_finalize_kernel(int64_t nvox, const float *__restrict__ acc, 
 // ((STW-1) sx, (STH-1) sy) mm, so along every axis the voxel box of a tile is at most
 // floor(d) + 3 voxels wide for d = that diagonal in voxels, whatever the pose; capped at
 // kSplatWin (tiles beyond the cap take the direct path).
+// Fixed-point unit exponent kw of the forward window.  A pixel adds to a voxel only if
+// its coordinate lies within one voxel of the voxel's centre along every axis, i.e. in a
+// cube of side 2 s mm; the frame plane cuts that cube inside a disc of radius sqrt(3) s,
+// which holds at most term_max = (floor(2 sqrt(3) s / sx) + 1)(floor(2 sqrt(3) s / sy) + 1)
+// pixel centres.  With every term at most 2^kw in magnitude, kw = 30 - ceil(log2 term_max)
+// keeps a voxel's sum within 2^30.
+// Below this unit (pixels so much smaller than voxels that over 2^10 of them can reach one
+// voxel) the rounding of each term would no longer be negligible: such frames skip the
+// window and add their terms with FP32 global atomics.
+constexpr int kMinKw = 20;
+
+int splat_kw(const SplatGeom &g) {
+  const double r2 = 2.0 * std::sqrt(3.0) * g.s;
+  const double tx = std::floor(r2 / g.sx) + 1.0, ty = std::floor(r2 / g.sy) + 1.0;
+  const double tmax = tx * ty;
+  if (!(tmax < 1e9)) return 1;
+  int bits = 0;
+  while ((double)(1 << bits) < tmax && bits < 29) ++bits;
+  return 30 - bits;
+}
+
 int splat_window_cap(const SplatGeom &g) {
   const double a = (STW - 1) * g.sx, b = (STH - 1) * g.sy;
   const double d = std::sqrt(a * a + b * b) / g.s;
@@ -665,9 +699,10 @@ hipError_t launch_splat_forward(const SplatGeom &g, const float *I, const double
   hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(vols), 4 * nvox, s);
   if (e != hipSuccess || F <= 0) return e;
   const int blocks = F * g.tiles_x * g.tiles_y;
-  const int cap = splat_window_cap(g);
-  hipLaunchKernelGGL(splat_fwd_kernel<false>, dim3(blocks), dim3(256), (size_t)cap * 16, s, g, (const void *)I,
-                     (int64_t)g.W, (int64_t)g.W * g.H, Mq, vols, 0, cap);
+  const int kw = splat_kw(g);
+  const int cap = kw >= kMinKw ? splat_window_cap(g) : 0;
+  hipLaunchKernelGGL(splat_fwd_kernel<false>, dim3(blocks), dim3(256), (size_t)cap * 8, s, g, (const void *)I,
+                     (int64_t)g.W, (int64_t)g.W * g.H, Mq, vols, 0, cap, kw);
   return hipGetLastError();
 }
 
@@ -677,7 +712,7 @@ hipError_t launch_dw_ingest(const SplatGeom &g, const uint8_t *I, int64_t row_pi
   const int blocks = F * g.tiles_x * g.tiles_y;
   const int cap = splat_window_cap(g);
   hipLaunchKernelGGL(splat_fwd_kernel<true>, dim3(blocks), dim3(256), (size_t)cap * 16, s, g, (const void *)I,
-                     row_pitch, frame_pitch, Mq, acc, 1, cap);
+                     row_pitch, frame_pitch, Mq, acc, 1, cap, 30);
   return hipGetLastError();
 }
 

@@ -45,6 +45,16 @@ def test_forward_small_and_reduced_cfg5():
     check_forward(synth.cfg5(n_frames=64, dims=(256, 192, 64)))
 
 
+def test_forward_dense_pixels_take_the_direct_path():
+    # 0.02 mm pixels in 0.5 mm voxels: about 7,600 pixels of one frame can reach a voxel,
+    # too many for the 32-bit fixed-point window, so the tiles add their terms with FP32
+    # global atomics; same tolerance against the FP64 oracle
+    say("case: dense pixels, direct forward path")
+    c = synth.cfg5(n_frames=6, W=120, H=96, px=0.02, dims=(8, 8, 6))
+    c["I"] = np.random.default_rng(8).uniform(-1.0, 1.0, c["I"].shape).astype(np.float32)
+    check_forward(c)
+
+
 def test_forward_unit_cases():
     say("case: voxel-centre pixels")
     F, H, W = 4, 6, 7
