@@ -21,10 +21,14 @@
 // returns a value: a wrapped u16 count is found afterwards by comparing the sum of the
 // stored counts with the kept-pixel total.
 //
-// Cost model (measured): device-scope atomics are performed beyond the XCD's L2, one
-// request per 64-byte segment a wave instruction touches, at ~25 G requests/s; a tilted
-// frame crosses each voxel row in runs of ~1 / tan(tilt) voxels, so the flush costs about
-// two requests per run and dominates the kernel.  Wider tiles split fewer runs.
+// Cost model (measured on the whole-spine sweep, 64-frame launches): about half of a
+// launch is the dependent chain from the launch arguments to the pixel loads, a quarter
+// the pixel phase (about 11 VALU instructions per pixel, issue-bound) and a quarter the
+// flush.  Device-scope atomics are performed beyond the XCD's L2, one request per 64-byte
+// segment a wave instruction touches, at ~23 G requests/s; a tilted frame crosses each
+// voxel row in runs of ~1 / tan(tilt) voxels, so the flush costs about two requests per
+// run, and every frame tile flushes the segments it reaches.  Wider tiles split fewer
+// runs.
 #include "usv_internal.h"
 
 namespace usv {
