@@ -425,6 +425,52 @@ def test_finalize_outputs_at_any_alignment(offsets):
     assert (bufV[:ov] == 0xAB).all() and (bufV[ov + n:] == 0xAB).all()
 
 
+def test_finalize_after_overlapped_sweeps_in_any_order():
+    """Finalize right after overlapped ingest on a grid of 320 planes: sweeps up z, down z,
+    up and back down, and in shuffled order (so early and late launches share planes),
+    each after a reset beside the previous projection and with no host synchronisation in
+    between, give the oracle's volume and state."""
+    from paper_2412_00058_amd import SEG_ALG2, seg_params
+    say("case: finalize after overlapped sweeps in any order")
+    W, H, px = 96, 64, 0.3
+    probe = synth.Probe(W, H, (px, px))
+    g = synth.Grid((48, 40, 320), (0.0, 0.0, 0.0), 0.5)
+    nx, ny, nz = g.dims
+    F = 160
+    gen = synth.rng(77, 0, 0)
+    poses = np.empty((F, 4, 4))
+    for n in range(F):
+        ang = gen.uniform(-4.0, 4.0, size=3) * np.pi / 180.0
+        poses[n] = synth.probe_pose((12.0 + gen.uniform(-1.0, 1.0), 1.0, 4.0 + 150.0 * n / (F - 1)), ang,
+                                    (W * px / 2.0, 0.0, 0.0))
+    frames = synth.rng(77, 1, 0).integers(0, 256, size=(F, H, W)).astype(np.uint8)
+    orders = [np.arange(F), np.arange(F)[::-1].copy(), np.concatenate([np.arange(F), np.arange(F - 1, F // 3, -1)]),
+              synth.rng(77, 2, 0).permutation(F)]
+    vol = gpu_volume(g)
+    pid = add_probe(vol, probe)
+    vol.set_ingest_overlap(True)
+    fr = to_dev(frames)
+    prm = seg_params(mode=SEG_ALG2, y_lo=1, k=6, tau_I=128, tau_G=30, r=2, fallback_y=20, half=(2, 5))
+    outs = []
+    for idx in orders:
+        vol.reset()
+        ti = torch.from_numpy(idx).to(fr.device)
+        for k in range(0, len(idx), 8):
+            vol.ingest(pid, fr[ti[k:k + 8]].contiguous(), poses[idx[k:k + 8]])
+        V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+        S = torch.empty_like(V)
+        vol.finalize(out=(V, S))
+        vol.segment_project(prm, V, S)
+        outs.append((V, S))
+    vol.sync()
+    for j, (idx, (V, S)) in enumerate(zip(orders, outs)):
+        acc = oracle.Accum(g)
+        acc.ingest(frames[idx], poses[idx], probe)
+        Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+        assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So), j
+    vol.close()
+
+
 def test_reset_beside_projection():
     """With overlap on, a reset that follows finalize (and segment_project) zeroes the
     accumulators on a library stream beside the projection.  Three sweeps in the
