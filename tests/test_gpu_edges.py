@@ -452,11 +452,12 @@ def test_finalize_after_overlapped_sweeps_in_any_order():
     fr = to_dev(frames)
     prm = seg_params(mode=SEG_ALG2, y_lo=1, k=6, tau_I=128, tau_G=30, r=2, fallback_y=20, half=(2, 5))
     outs = []
-    for idx in orders:
+    # the frames of a burst are in place before it starts and stay alive until it is joined
+    gathered = [fr[torch.from_numpy(idx).to(fr.device)].contiguous() for idx in orders]
+    for idx, fo in zip(orders, gathered):
         vol.reset()
-        ti = torch.from_numpy(idx).to(fr.device)
         for k in range(0, len(idx), 8):
-            vol.ingest(pid, fr[ti[k:k + 8]].contiguous(), poses[idx[k:k + 8]])
+            vol.ingest(pid, fo[k:k + 8], poses[idx[k:k + 8]])
         V = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
         S = torch.empty_like(V)
         vol.finalize(out=(V, S))
