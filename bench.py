@@ -740,7 +740,7 @@ def main():
     # tile shape picked by the library's autotuner on the first 1024 frames (untimed); the
     # choice is cached in a temp file so that profiled passes reuse it without re-tuning
     import tempfile
-    # consecutive ingest launches overlap on two library streams (joined before finalize);
+    # consecutive ingest launches overlap on the library's side streams (joined before finalize);
     # the tile is tuned in that mode; the profile pass and the roofline's launch timing
     # then run the launches one after another with the same tile
     vol.set_ingest_overlap(not args.serial)
@@ -1010,7 +1010,7 @@ def main():
                                   "+-20 mm meander and +-5 deg jitter, grid 400x240x1120 @ 0.5 mm, calls of 64 "
                                   "frames, full finalize, ALG2 depth + slab projection h=2/5/10",
                       "tile": list(tile), "frames_per_launch": frames_per_launch,
-                      "ingest_streams": 1 if args.serial else 2, "parallelism": "single GPU"},
+                      "ingest_streams": 1 if args.serial else usv.INGEST_STREAMS, "parallelism": "single GPU"},
            "breakdown_ms": {"ingest": round(phase[0], 4), "finalize": round(phase[1], 4),
                             "segment_project": round(phase[2], 4)},
            "event_ms_per_step": {"median": round(float(np.median(ev_ms)), 4), "min": round(float(np.min(ev_ms)), 4),

@@ -177,7 +177,7 @@ usv_status usv_ingest_frames(usv_volume *vol, int32_t probe_id, const uint8_t *f
 /* Overlapped ingest (off by default).  Consecutive ingest launches of one volume are
  * independent (integer atomics commute), but launches on one stream run back to back,
  * each leaving the GPU partly idle at its start and end.  With overlap on, ingest
- * launches rotate over three library streams (default priority).  A burst of
+ * launches rotate over USV_INGEST_STREAMS library streams (default priority).  A burst of
  * ingest calls starts at the first ingest call after a join: the side streams then wait
  * for everything enqueued on the volume's stream so far, and later calls of the burst
  * add no waits (no host synchronisation calls per launch), so work the caller enqueues
@@ -185,10 +185,12 @@ usv_status usv_ingest_frames(usv_volume *vol, int32_t probe_id, const uint8_t *f
  * burst ends when the volume's stream waits for the side streams: at the next call of
  * another kind on this volume (finalize, segment_project, sync, reset, export / import,
  * autotune, graph calls, batched ingest) or at usv_join.  Until then the frames of the
- * burst must stay unchanged and the accumulators must not be read; results are
+ * burst must be in place when it starts and stay unchanged and allocated until it ends,
+ * and the accumulators must not be read; results are
  * identical to the serial order.  Turning overlap off joins.  usv_finalize enqueues its
  * zero fill of the outputs outside the live box (it reads no accumulator) before it
  * joins, so that fill may run beside the burst's last launches. */
+#define USV_INGEST_STREAMS 3
 usv_status usv_set_ingest_overlap(usv_volume *vol, int32_t enable);
 /* make the volume's stream wait for any overlapped ingest launches (enqueue only) */
 usv_status usv_join(usv_volume *vol);

@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kMaxProbes = 16;
 // library streams that consecutive ingest launches alternate between (overlapped ingest)
-constexpr int kSides = 3;
+constexpr int kSides = USV_INGEST_STREAMS;
 constexpr int64_t kMaxVox = (int64_t)1 << 31;
 constexpr double kMapLimit = 18446744073709551616.0;  // 2^64
 
@@ -83,8 +83,8 @@ struct usv_volume {
   // voxel box outside which every accumulator is zero (empty after a reset; the whole
   // grid at creation and after an import)
   usv_box touched{};
-  // overlapped ingest (usv_set_ingest_overlap): launches alternate between two library
-  // streams that wait for `stream` at each launch; `stream` waits for them lazily
+  // overlapped ingest (usv_set_ingest_overlap): launches rotate over kSides library
+  // streams that wait for `stream` once per burst; `stream` waits for them lazily
   bool overlap = false;
   hipStream_t side[kSides] = {};
   hipEvent_t side_ev[kSides] = {};
@@ -175,7 +175,7 @@ usv_status quiesce(usv_volume *v) {
 }
 
 // Stream of the next ingest launch: the volume stream, or (overlap) the next side stream.
-// The first launch of a burst (after a join) makes both side streams wait for everything
+// The first launch of a burst (after a join) makes every side stream wait for everything
 // enqueued on the volume stream so far; later launches of the burst add no host calls.
 hipStream_t ingest_stream(usv_volume *v) {
   if (!v->overlap) return v->stream;
@@ -193,7 +193,7 @@ hipStream_t ingest_stream(usv_volume *v) {
   return v->side[v->next_side];
 }
 
-// After a launch on ingest_stream(v): the next launch goes to the other side stream.
+// After a launch on ingest_stream(v): the next launch goes to the next side stream.
 void ingest_launched(usv_volume *v) {
   if (v->overlap) v->next_side = v->next_side + 1 == kSides ? 0 : v->next_side + 1;
 }

@@ -17,6 +17,7 @@ from ._lib import Box, CutParams, GridDesc, ProbeDesc, RefineParams, SegParams, 
 
 SEG_ALG2, SEG_ALG1, SEG_FIXED = 0, 1, 2
 EMPTY, MEASURED, FILLED = 0, 1, 2
+INGEST_STREAMS = 3   # USV_INGEST_STREAMS: side streams of overlapped ingest
 
 
 def _vp(t) -> C.c_void_p:
@@ -233,8 +234,9 @@ class Volume:
         return box
 
     def set_ingest_overlap(self, enable: bool = True):
-        """Overlap consecutive ingest launches on two library streams (frames of pending
-        calls must stay unchanged until the next non-ingest call or join())."""
+        """Overlap consecutive ingest launches on INGEST_STREAMS library streams (the frames
+        of a burst must be in place when it starts and stay unchanged and allocated until
+        the next non-ingest call or join())."""
         check(lib().usv_set_ingest_overlap(self.h, 1 if enable else 0), self.h)
 
     def join(self):

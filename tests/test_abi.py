@@ -32,6 +32,11 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in U.version()
 
 
+def test_header_constants_match_the_binding():
+    txt = open(os.path.join(ROOT, "include", "usv.h")).read()
+    assert int(re.search(r"#define USV_INGEST_STREAMS (\d+)", txt).group(1)) == U.INGEST_STREAMS
+
+
 def test_accumulator_bytes_and_grid_validation():
     assert U.accumulator_bytes((3, 1, 1)) == 4 * 3 + 2 * 4
     assert U.accumulator_bytes((400, 240, 1120)) == 6 * 107520000
