@@ -1334,13 +1334,21 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
     p.t = t;
     p.chunk = chunk;
     if (upload_tile_class(p) != hipSuccess) return -1.0f;
-    // the frame split depends on the candidate's LDS packing
+    // one timed run submits the sample the way callers stream frames: calls of
+    // kLaunchFrames frames, each folding its poses on the host and then launching (so the
+    // host's share of smaller launches is part of the time); the frame split depends on
+    // the candidate's LDS packing
     std::vector<float> maps, smaps;
     std::vector<int32_t> fidx, sfidx;
-    if (prepare_frames(v, p, poses, n, maps, fidx, nullptr, &smaps, &sfidx) != USV_OK) return -1.0f;
     auto run = [&]() {
-      usv_status r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, maps, fidx);
-      if (r == USV_OK && !sfidx.empty()) r = launch_frames(&tmp, p, frames, row_pitch, frame_pitch, smaps, sfidx, true);
+      usv_status r = USV_OK;
+      for (int32_t c0 = 0; c0 < n && r == USV_OK; c0 += kLaunchFrames) {
+        const int32_t cnt = std::min<int32_t>(kLaunchFrames, n - c0);
+        const uint8_t *fc = frames + (int64_t)c0 * frame_pitch;
+        r = prepare_frames(v, p, poses + 16 * (size_t)c0, cnt, maps, fidx, nullptr, &smaps, &sfidx);
+        if (r == USV_OK) r = launch_frames(&tmp, p, fc, row_pitch, frame_pitch, maps, fidx);
+        if (r == USV_OK && !sfidx.empty()) r = launch_frames(&tmp, p, fc, row_pitch, frame_pitch, smaps, sfidx, true);
+      }
       const usv_status j = join_side(&tmp);
       return r != USV_OK ? r : j;
     };
