@@ -94,3 +94,84 @@ def test_batched_all_16_sweeps_after_autotune():
         assert_accum_equal(vol, acc, "batched sweep %d" % i)
     for j in jobs:
         j[0].close()
+
+
+def test_largest_grid_far_corner():
+    """The largest grid the library takes (2048 x 1024 x 1023 voxels, just under 2^31, so
+    12.9 GB of accumulators and byte offsets above 2^32): frames at its far corner, partly
+    outside the three far faces, in one call of 3 and one of 97 frames (two launches).
+    Accumulators, volume and state over the touched box dilated by two equal the oracle's
+    bit for bit and are zero / EMPTY everywhere else; depth and slab projections of the
+    columns around the sweep equal the oracle's on the same sub-volume, and every other
+    column holds the no-data result."""
+    from paper_2412_00058_amd import SEG_ALG2, Volume, seg_params
+    say("case: largest grid, far corner")
+    g = synth.Grid((2048, 1024, 1023), (0.0, 0.0, 0.0), 0.5)
+    nx, ny, nz = g.dims
+    assert 2 ** 31 - 2 ** 22 < g.nvox < 2 ** 31
+    W, H, px = 128, 96, 0.3
+    probe = synth.Probe(W, H, (px, px))
+    F = 100
+    gen = synth.rng(91, 0, 0)
+    poses = np.empty((F, 4, 4))
+    for n in range(F):
+        ang = gen.uniform(-10.0, 10.0, size=3) * np.pi / 180.0
+        poses[n] = synth.probe_pose((1010.0 + gen.uniform(-2.0, 2.0), 490.0, 470.0 + 0.45 * n), ang,
+                                    (W * px / 2.0, 0.0, 0.0))
+    frames = synth.rng(91, 1, 0).integers(0, 120, size=(F, H, W)).astype(np.uint8)
+    frames[:, 40:51, :] = 230   # a bright band over darker rows for the contour scan
+    sk = dict(y_lo=0, k=6, tau_I=128, tau_G=30, r=2, fallback_y=1000, half=(2, 5, 10))
+    vol = Volume(g.dims, g.origin_mm, g.voxel_mm)
+    pid = vol.add_probe(W, H, (px, px))
+    fr = torch.from_numpy(frames).cuda()
+    b1 = vol.ingest(pid, fr[:3], poses[:3])
+    b2 = vol.ingest(pid, fr[3:], poses[3:])
+    V, S = vol.finalize()
+    dep, mean, mx = vol.segment_project(seg_params(mode=SEG_ALG2, **sk), V, S)
+    vol.sync()
+    lo = [max(0, min(b1.lo[k], b2.lo[k]) - 2) for k in range(3)]
+    hi = [min(g.dims[k], max(b1.hi[k], b2.hi[k]) + 2) for k in range(3)]
+    assert [max(b1.hi[k], b2.hi[k]) for k in range(3)] == [nx, ny, nz], "the sweep reaches the far faces"
+    (x0, y0, z0), (x1, y1, z1) = lo, hi
+    say("  box", lo, hi)
+    acc = oracle.Accum(g)   # lazily zeroed pages: only the touched ones are materialised
+    acc.ingest(frames, poses, probe)
+    so = acc.sum.reshape(nz, ny, nx)[z0:z1, y0:y1, x0:x1].copy()
+    co = acc.cnt.reshape(nz, ny, nx)[z0:z1, y0:y1, x0:x1].copy()
+    del acc
+    assert co.sum() > 100000
+    sg = vol.sum.view(nz, ny, nx)[z0:z1, y0:y1, x0:x1].cpu().numpy().view(np.uint32)
+    cg = vol.cnt.view(nz, ny, nx)[z0:z1, y0:y1, x0:x1].cpu().numpy().view(np.uint16)
+    assert np.array_equal(sg, so) and np.array_equal(cg, co)
+    assert int(torch.count_nonzero(vol.sum)) == int(np.count_nonzero(so))
+    assert int(torch.count_nonzero(vol.cnt)) == int(np.count_nonzero(co))
+    # normalise + fill is translation invariant: the oracle on the box alone (its near
+    # faces lie two voxels beyond anything touched; its far faces are the grid's)
+    bg = synth.Grid((x1 - x0, y1 - y0, z1 - z0), (0.0, 0.0, 0.0), 0.5)
+    Vo, So, _ = oracle.finalize(bg, so.ravel(), co.ravel())
+    assert np.array_equal(V[z0:z1, y0:y1, x0:x1].cpu().numpy(), Vo)
+    assert np.array_equal(S[z0:z1, y0:y1, x0:x1].cpu().numpy(), So)
+    assert int(torch.count_nonzero(V)) == int(np.count_nonzero(Vo))
+    assert int(torch.count_nonzero(S)) == int(np.count_nonzero(So))
+    # Alg. 2 depth and slabs on the columns [xs, nx) x [zs, nz) over all rows, from the
+    # oracle's own volume; columns within r of the sub-volume's near edges see a clipped
+    # median window there and are left out
+    r = sk["r"]
+    xs, zs = max(0, x0 - r - 2), max(0, z0 - r - 2)
+    Vs = np.zeros((nz - zs, ny, nx - xs), np.uint8)
+    Ss = np.zeros_like(Vs)
+    Vs[z0 - zs:z1 - zs, y0:y1, x0 - xs:x1 - xs] = Vo
+    Ss[z0 - zs:z1 - zs, y0:y1, x0 - xs:x1 - xs] = So
+    sg_ = synth.Grid((nx - xs, ny, nz - zs), (0.0, 0.0, 0.0), 0.5)
+    do, mo, xo = oracle.segment(sg_, Vs, Ss, oracle.seg_params(mode=oracle.ALG2, **sk))
+    dh, mh, xh = dep.cpu().numpy(), mean.cpu().numpy(), mx.cpu().numpy()
+    assert np.array_equal(dh[zs + r:, xs + r:], do[r:, r:])
+    assert np.array_equal(mh[:, zs + r:, xs + r:].view(np.uint32), mo[:, r:, r:].view(np.uint32))
+    assert np.array_equal(xh[:, zs + r:, xs + r:].view(np.uint32), xo[:, r:, r:].view(np.uint32))
+    # every column away from the sweep: the oracle's no-data column
+    nd = (do[0, 0], mo[:, 0, 0].view(np.uint32), xo[:, 0, 0].view(np.uint32))
+    assert (dh[:zs, :] == nd[0]).all() and (dh[:, :xs] == nd[0]).all()
+    for a, b in ((mh, nd[1]), (xh, nd[2])):
+        av = a.view(np.uint32)
+        assert (av[:, :zs, :] == b[:, None, None]).all() and (av[:, :, :xs] == b[:, None, None]).all()
+    vol.close()
