@@ -2,7 +2,8 @@
 the oracle bit for bit: 512 whole-spine frames (480 x 640) through captured-graph launches,
 the same frames through the real-time pipeline with a render every 10 frames, and all 16
 sweeps of the batched workload (linear and convex probes, each into its own grid, the
-first 256 frames of each) through one batched call after autotuning each probe."""
+first 256 frames of each) through one batched call after autotuning each probe; and the
+largest grid the library takes, with frames at its far corner."""
 import numpy as np
 import pytest
 import torch
