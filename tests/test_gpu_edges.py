@@ -160,6 +160,50 @@ def test_whole_spine_sweep_full_size_bit_exact():
     assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32))
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 6, 4), (5, 1, 3), (2, 2, 1), (7, 3, 1), (3, 9, 2)])
+@pytest.mark.parametrize("wh", [(1, 1), (3, 2), (24, 20)])
+def test_degenerate_grids_and_probes(dims, wh):
+    """Grids one voxel thick along any axis (down to a single voxel) and images of 1 x 1
+    and 3 x 2 pixels: ingest, normalise + fill and Alg. 2 depth / slabs (no rows to scan
+    when the grid is shallower than the window) equal the oracle's bit for bit."""
+    from paper_2412_00058_amd import SEG_ALG2, seg_params
+    W, H = wh
+    say("case: degenerate grid", dims, "image", wh)
+    nx, ny, nz = dims
+    px = 0.25
+    g = synth.Grid(dims, (0.0, 0.0, 0.0), 1.0)
+    probe = synth.Probe(W, H, (px, px))
+    gen = synth.rng(95, nx * 100 + ny * 10 + nz, W * 100 + H)
+    F = 40
+    poses = np.empty((F, 4, 4))
+    for n in range(F):
+        ang = gen.uniform(-30.0, 30.0, size=3) * np.pi / 180.0
+        c = np.array([gen.uniform(0.0, nx), gen.uniform(0.0, ny), gen.uniform(0.0, nz)])
+        poses[n] = synth.probe_pose(c, ang, (W * px / 2.0, H * px / 2.0, 0.0))
+    frames = synth.rng(95, 1, W * 100 + H).integers(0, 256, size=(F, H, W)).astype(np.uint8)
+    vol = gpu_volume(g)
+    pid = add_probe(vol, probe)
+    fr = to_dev(frames)
+    vol.ingest(pid, fr[:7], poses[:7])
+    vol.ingest(pid, fr[7:], poses[7:])
+    V, S = vol.finalize()
+    sk = dict(y_lo=0, k=1, tau_I=100, tau_G=10, r=1, fallback_y=0, half=(0, 1))
+    dep, mean, mx = vol.segment_project(seg_params(mode=SEG_ALG2, **sk), V, S)
+    vol.sync()
+    acc = oracle.Accum(g)
+    acc.ingest(frames, poses, probe)
+    assert_accum_equal(vol, acc, "degenerate %s %s" % (dims, wh))
+    if W * H > 1:
+        assert acc.cnt.sum() > 0, "the frames reach the grid"
+    Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    do, mo, xo = oracle.segment(g, Vo, So, oracle.seg_params(mode=oracle.ALG2, **sk))
+    assert np.array_equal(dep.cpu().numpy(), do)
+    assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32))
+    assert np.array_equal(mx.cpu().numpy().view(np.uint32), xo.view(np.uint32))
+    vol.close()
+
+
 def test_segment_project_odd_width_grid():
     """A grid width that is not a multiple of 4 takes the one-column-per-lane depth scan."""
     from paper_2412_00058_amd import seg_params, SEG_ALG1, SEG_ALG2, SEG_FIXED
