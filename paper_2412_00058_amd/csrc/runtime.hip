@@ -101,6 +101,10 @@ struct usv_volume {
   bool acc_quiet = false;      // nothing has touched the accumulators since acc_ev
   bool unfinalized = false;    // pixels added (or accumulators imported) since the last finalize / reset
   bool zero_pending = false;   // side streams 1 .. kSides - 1 have not yet waited for zero_ev
+  // host scratch of usv_ingest_frames (maps and frame indices of the plain and the
+  // small-tile launches), kept so that a call allocates nothing once warm
+  std::vector<float> call_maps, call_smaps;
+  std::vector<int32_t> call_fidx, call_sfidx;
 };
 
 struct usv_graph {
@@ -265,13 +269,14 @@ bool frame_box_rows(const float M[9], int W, int vlo, int vhi, const int n[3], i
     const float m0 = M[3 * r], m1 = M[3 * r + 1], m2 = M[3 * r + 2];
     const float umin = m0 >= 0.0f ? u0 : u1, umax = m0 >= 0.0f ? u1 : u0;
     const float vmin = m1 >= 0.0f ? v0 : v1, vmax = m1 >= 0.0f ? v1 : v0;
-    volatile float a = m0 * umin, t = m1 * vmin;
-    volatile float c = t + m2;
-    volatile float qmin = a + c;
+    // each operation rounds to FP32 on its own (the library is built without contraction)
+    float a = m0 * umin, t = m1 * vmin;
+    float c = t + m2;
+    const float qmin = a + c;
     a = m0 * umax;
     t = m1 * vmax;
     c = t + m2;
-    volatile float qmax = a + c;
+    const float qmax = a + c;
     const float nf = (float)n[r];
     if (qmax < 0.0f || qmin >= nf) return false;
     lo[r] = qmin >= 0.0f ? (int)qmin : 0;
@@ -470,6 +475,8 @@ usv_status prepare_frames(usv_volume *v, const ProbeState &p, const double *pose
   if (sfidx) sfidx->clear();
   if (rows) rows->clear();
   if (srows) srows->clear();
+  maps.reserve(9 * (size_t)n);
+  fidx.reserve((size_t)n);
   usv_box b = empty_box();
   const int dims[3] = {v->nx, v->ny, v->nz};
   for (int32_t i = 0; i < n; ++i) {
@@ -885,8 +892,8 @@ usv_status usv_ingest_frames(usv_volume *v, int32_t probe_id, const uint8_t *fra
     return fail(v, USV_E_ARG, "pitch smaller than the image");
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   if (n == 0) return USV_OK;
-  std::vector<float> maps, smaps;
-  std::vector<int32_t> fidx, sfidx;
+  std::vector<float> &maps = v->call_maps, &smaps = v->call_smaps;
+  std::vector<int32_t> &fidx = v->call_fidx, &sfidx = v->call_sfidx;
   usv_box box = empty_box();
   usv_status st = prepare_frames(v, p, poses, n, maps, fidx, &box, &smaps, &sfidx);
   if (st != USV_OK) return st;
