@@ -178,7 +178,11 @@ class Volume:
         h = C.c_void_p()
         check(L.usv_create_volume(C.byref(self.desc), _vp(self.acc), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
-        self._keep = []
+        self._overlap = False
+        # frames of the pending overlapped burst: referenced until a call that joins it, so
+        # the caching allocator does not hand their memory out while a library stream may
+        # still read it (after the join, the volume's stream is ordered behind the burst)
+        self._burst_frames = []
         self._probe_hw = {}   # probe id -> (rows, columns) of its images
 
     def close(self):
@@ -221,6 +225,7 @@ class Volume:
 
     def set_tiling(self, probe_id, tile_w, tile_h):
         check(lib().usv_probe_set_tiling(self.h, probe_id, int(tile_w), int(tile_h)), self.h)
+        self._joined()
 
     def ingest(self, probe_id, frames: torch.Tensor, poses) -> Box:
         """frames: uint8 device tensor [F, H, W] (row pitch = stride); poses [F, 4, 4] FP64 host."""
@@ -231,16 +236,27 @@ class Volume:
         box = Box()
         check(lib().usv_ingest_frames(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                       P.ctypes.data_as(C.c_void_p), n, C.byref(box)), self.h)
+        if self._overlap:
+            self._burst_frames.append(frames)
         return box
 
     def set_ingest_overlap(self, enable: bool = True):
-        """Overlap consecutive ingest launches on INGEST_STREAMS library streams (the frames
-        of a burst must be in place when it starts and stay unchanged and allocated until
-        the next non-ingest call or join())."""
+        """Overlap consecutive ingest launches on INGEST_STREAMS library streams.  The frames
+        of a burst must be in place when it starts (work enqueued on the volume's stream
+        after the burst's first call is not waited for) and unchanged until the next
+        non-ingest call or join(); this binding keeps the frames tensors referenced until
+        then, so dropping them earlier is safe."""
         check(lib().usv_set_ingest_overlap(self.h, 1 if enable else 0), self.h)
+        self._joined()
+        self._overlap = bool(enable)
+
+    def _joined(self):
+        """The library has ordered the volume's stream behind any pending overlapped burst."""
+        self._burst_frames.clear()
 
     def join(self):
         check(lib().usv_join(self.h), self.h)
+        self._joined()
 
     def ingest_cut(self, probe_id, frames: torch.Tensor, poses, rows) -> Box:
         """ingest() restricted to each frame's band of rows (int32 [F, 2] first/last row,
@@ -255,6 +271,8 @@ class Volume:
         check(lib().usv_ingest_frames_cut(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                           P.ctypes.data_as(C.c_void_p), R.ctypes.data_as(C.c_void_p), n,
                                           C.byref(box)), self.h)
+        if self._overlap:
+            self._burst_frames.append(frames)
         return box
 
     def finalize(self, region: Optional[Box] = None, out=None, with_state=True):
@@ -268,6 +286,7 @@ class Volume:
             if S is not None:
                 _check_buf(S, torch.uint8, self.nvox, "finalize output state")
         check(lib().usv_finalize(self.h, C.byref(region) if region is not None else None, _vp(V), _vp(S)), self.h)
+        self._joined()
         return V, S
 
     def segment_project(self, params: SegParams, V, S, out=None):
@@ -286,34 +305,42 @@ class Volume:
             _check_buf(mx, torch.float32, params.n_half * nz * nx, "segment output max")
         check(lib().usv_segment_project(self.h, C.byref(params), _vp(V), _vp(S), _vp(depth), _vp(mean), _vp(mx)),
               self.h)
+        self._joined()
         return depth, mean, mx
 
     def sync(self):
         check(lib().usv_sync(self.h), self.h)
+        self._joined()
 
     def status(self) -> int:
-        return int(lib().usv_sync(self.h))
+        st = int(lib().usv_sync(self.h))
+        self._joined()
+        return st
 
     def reset(self):
         check(lib().usv_reset(self.h), self.h)
+        self._joined()
 
     def export_accumulators(self, dst: Optional[torch.Tensor] = None) -> torch.Tensor:
         dst = torch.empty_like(self.acc) if dst is None else dst
         _need(isinstance(dst, torch.Tensor) and dst.is_cuda and dst.is_contiguous() and
               dst.numel() * dst.element_size() >= self.acc.numel() * 4, "export: device buffer of the accumulator size")
         check(lib().usv_export_accumulators(self.h, _vp(dst)), self.h)
+        self._joined()
         return dst
 
     def import_accumulators(self, src: torch.Tensor):
         _need(isinstance(src, torch.Tensor) and src.is_cuda and src.is_contiguous() and
               src.numel() * src.element_size() >= self.acc.numel() * 4, "import: device buffer of the accumulator size")
         check(lib().usv_import_accumulators(self.h, _vp(src)), self.h)
+        self._joined()
 
     def autotune(self, probe_id, frames: torch.Tensor, poses, cache_path: Optional[str] = None):
         P = _poses(poses)
         check(lib().usv_autotune(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                  P.ctypes.data_as(C.c_void_p), frames.shape[0],
                                  cache_path.encode() if cache_path else None), self.h)
+        self._joined()
         return self.tiling(probe_id)
 
     def host_accumulators(self):
@@ -326,7 +353,8 @@ class Volume:
 
 def ingest_batched(jobs: Sequence[tuple]):
     """jobs: sequence of (Volume, probe_id, frames uint8 [F,H,W] device tensor, poses [F,4,4]).
-    One persistent launch on the first volume's stream.  Returns the dirty boxes."""
+    One launch (one block per (sweep, frame, tile) item) on the first volume's stream, after
+    any pending overlapped burst of the volumes is joined.  Returns the dirty boxes."""
     n = len(jobs)
     L = lib()
     vols = (C.c_void_p * n)(*[j[0].h for j in jobs])
@@ -339,6 +367,8 @@ def ingest_batched(jobs: Sequence[tuple]):
     nf = (C.c_int32 * n)(*[int(j[2].shape[0]) for j in jobs])
     boxes = (Box * n)()
     check(L.usv_ingest_batched(vols, pids, frames, rp, fp, pp, nf, n, boxes), jobs[0][0].h)
+    for j in jobs:
+        j[0]._joined()
     return list(boxes)
 
 
@@ -348,6 +378,7 @@ class Graph:
     def __init__(self, vol: Volume, probe_id: int):
         h = C.c_void_p()
         check(lib().usv_graph_create(vol.h, probe_id, C.byref(h)), vol.h)
+        vol._joined()
         self.h = h
         self.vol = vol
 
@@ -357,6 +388,7 @@ class Graph:
         box = Box()
         check(lib().usv_graph_launch(self.h, f.ctypes.data_as(C.c_void_p), P.ctypes.data_as(C.c_void_p),
                                      C.byref(box)), self.vol.h)
+        self.vol._joined()
         return box
 
     def close(self):

@@ -516,6 +516,38 @@ def test_finalize_after_overlapped_sweeps_in_any_order():
     vol.close()
 
 
+def test_binding_holds_burst_frames_until_the_join():
+    """Overlapped ingest reads a call's frames on a library stream after the call returns.
+    The binding keeps the frames tensors of a pending burst referenced until a call that
+    joins it, so a caller that drops its frames right after the calls, and allocates and
+    writes same-sized buffers on the volume's stream, still gets the oracle's result."""
+    say("case: binding holds burst frames")
+    d = synth.cfg1()
+    g = d["grid"]
+    vol = gpu_volume(g)
+    pid = add_probe(vol, d["probe"])
+    vol.set_tiling(pid, 32, 32)
+    vol.set_ingest_overlap(True)
+    fr = to_dev(d["frames"])
+    chunks = [fr[k:k + 8].clone() for k in range(0, 64, 8)]   # in place before the burst
+    torch.cuda.current_stream().synchronize()
+    for k, c in zip(range(0, 64, 8), chunks):
+        vol.ingest(pid, c, d["poses"][k:k + 8])
+    assert len(vol._burst_frames) == 8
+    del chunks, c
+    junk = [torch.full_like(fr[:8], 255) for _ in range(8)]   # may reuse freed blocks at once
+    V, S = vol.finalize()
+    assert len(vol._burst_frames) == 0
+    vol.sync()
+    del junk
+    acc = oracle.Accum(g)
+    acc.ingest(d["frames"], d["poses"], d["probe"])
+    assert_accum_equal(vol, acc, "frames dropped by the caller during the burst")
+    Vo, So, _ = oracle.finalize(g, acc.sum, acc.cnt)
+    assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
+    vol.close()
+
+
 def test_reset_beside_projection():
     """With overlap on, a reset that follows finalize (and segment_project) zeroes the
     accumulators on a library stream beside the projection.  Three sweeps in the
