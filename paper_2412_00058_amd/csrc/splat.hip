@@ -389,7 +389,8 @@ __device__ __forceinline__ void trigrad(const float c[8], float fx, float fy, fl
 __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float *__restrict__ I,
                                                         const double *__restrict__ Mq, const float *__restrict__ grads,
                                                         float *__restrict__ dI, double *__restrict__ partial) {
-  __shared__ __align__(16) float2 gwin[kSplatWin];
+  // entry kSplatWin stays zero: corners outside the grid read it
+  __shared__ __align__(16) float2 gwin[kSplatWin + 1];
   __shared__ float red[6][4];
   const int b = blockIdx.x;
   const int tc = b % g.tiles_x, rest = b / g.tiles_x;
@@ -426,6 +427,7 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
     const int v = v0 + ty0 + 8 * k;
     vals[k] = (any && u <= u1 && v <= v1) ? I[((int64_t)f * g.H + v) * g.W + u] : 0.0f;
   }
+  if (threadIdx.x == 0) gwin[kSplatWin] = make_float2(0.0f, 0.0f);
   if (staged) {
     // window entries in groups of kStage per thread: all loads of a group are issued
     // before its LDS stores (entries past the end re-read the last one and are not
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
   };
   if (staged) {
     // two pixels at a time: all 16 corner reads from LDS are issued before either
-    // pixel's terms are formed (reads of corners a pixel does not use go to entry 0)
+    // pixel's terms are formed (corners a pixel does not use read the zero entry)
 #pragma unroll
     for (int k2 = 0; k2 < kRowsPT; k2 += 2) {
       PixW p[2];
@@ -492,9 +494,9 @@ __global__ __launch_bounds__(256) void splat_bwd_kernel(SplatGeom g, const float
           const int bx = dlt & 1, by = (dlt >> 1) & 1, bz = dlt >> 2;
           const bool ok = in && (bx ? p[h].ok1[0] : p[h].ok0[0]) && (by ? p[h].ok1[1] : p[h].ok0[1]) &&
                           (bz ? p[h].ok1[2] : p[h].ok0[2]);
-          const float2 t = gwin[ok ? base + bx + by * wx + bz * wxy : 0];
-          gs[h][dlt] = ok ? t.x : 0.0f;
-          gw[h][dlt] = ok ? t.y : 0.0f;
+          const float2 t = gwin[ok ? base + bx + by * wx + bz * wxy : kSplatWin];
+          gs[h][dlt] = t.x;
+          gw[h][dlt] = t.y;
         }
       }
 #pragma unroll
