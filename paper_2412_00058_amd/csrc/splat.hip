@@ -27,7 +27,10 @@ namespace usv {
 namespace {
 
 constexpr int STW = 32, STH = 32;
-constexpr int kSplatWin = 2816;   // window entries per block (forward: two arrays of 32- or 64-bit words; backward: float2)
+constexpr int kSplatWin = 2816;
+// fixed-point exponent of the distance-weighted compounding: a run of four terms of at
+// most 2^kw each stays below 2^31 in a 32-bit register
+constexpr int kDwKw = 28;   // window entries per block (forward: two arrays of 32- or 64-bit words; backward: float2)
 
 __device__ void mat3_mul(const double *a, const double *b, double *c) {
   for (int i = 0; i < 3; ++i)
@@ -157,10 +160,12 @@ __device__ __forceinline__ void pixel_coord(const double *m, int u, int v, const
 // splat (FP32 intensities) keeps 32-bit words: the host picks kw so that the terms one
 // voxel can receive from one frame (at most term_max, below) sum to less than 2^31.  The
 // distance-weighted compounding (uint8 frames, kU8), whose volume S / W amplifies the
-// rounding where the weight is small, keeps 64-bit words with kw = 30 (no window sum
-// reaches 2^41).  The window (dynamic LDS, win_cap entries of S and of W, sized by the
-// host from the tile's largest possible voxel box) is flushed with FP32 global atomics of
-// the converted sums.
+// rounding where the weight is small, keeps 64-bit words with kw = 28 (no window sum
+// reaches 2^39).  Either way the terms of a lane's run (at most four pixels, each term at
+// most 2^kw <= 2^28 for kU8) sum in 32-bit registers and reach the window once per base
+// voxel.  The window (dynamic LDS, win_cap entries of S and of W, sized by the host from
+// the tile's largest possible voxel box) is flushed with FP32 global atomics of the
+// converted sums.
 template <bool kU8>
 __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void *__restrict__ Iv, int64_t row_pitch,
                                                         int64_t frame_pitch, const double *__restrict__ Mq,
@@ -242,7 +247,7 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
     // consecutive pixels of the run that share their base voxel add their fixed-point
     // terms in registers (integer sums: the same totals as one LDS atomic per term) and
     // reach the window once per base voxel
-    Acc aS[8], aW[8];
+    int aS[8], aW[8];
     int c0 = 0, c1 = 0, c2 = 0;
     uint32_t okm = 0u;   // bit d: corner d inside the grid
     bool open = false;
@@ -252,11 +257,11 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
         if (!(okm & (1u << dlt))) continue;
         const int e = (c0 + (dlt & 1) - lo[0]) + wx * ((c1 + ((dlt >> 1) & 1) - lo[1]) + wy * (c2 + (dlt >> 2) - lo[2]));
         if (kU8) {
-          atomicAdd(reinterpret_cast<unsigned long long *>(&win[e]), (unsigned long long)aS[dlt]);
-          atomicAdd(reinterpret_cast<unsigned long long *>(&winW[e]), (unsigned long long)aW[dlt]);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&win[e]), (unsigned long long)(long long)aS[dlt]);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&winW[e]), (unsigned long long)(long long)aW[dlt]);
         } else {
-          atomicAdd(reinterpret_cast<int *>(&win[e]), (int)aS[dlt]);
-          atomicAdd(reinterpret_cast<int *>(&winW[e]), (int)aW[dlt]);
+          atomicAdd(reinterpret_cast<int *>(&win[e]), aS[dlt]);
+          atomicAdd(reinterpret_cast<int *>(&winW[e]), aW[dlt]);
         }
       }
     };
@@ -291,8 +296,8 @@ __global__ __launch_bounds__(256) void splat_fwd_kernel(SplatGeom g, const void 
 #pragma unroll
       for (int dlt = 0; dlt < 8; ++dlt) {
         const float w = (dlt & 1 ? p.f[0] : gx0) * wyz[dlt >> 1];
-        aS[dlt] += (Acc)__float2int_rn(w * vs);
-        aW[dlt] += (Acc)__float2int_rn(w * sc_w);
+        aS[dlt] += __float2int_rn(w * vs);
+        aW[dlt] += __float2int_rn(w * sc_w);
       }
     }
     if (open) flush();
@@ -714,7 +719,7 @@ hipError_t launch_dw_ingest(const SplatGeom &g, const uint8_t *I, int64_t row_pi
   const int blocks = F * g.tiles_x * g.tiles_y;
   const int cap = splat_window_cap(g);
   hipLaunchKernelGGL(splat_fwd_kernel<true>, dim3(blocks), dim3(256), (size_t)cap * 16, s, g, (const void *)I,
-                     row_pitch, frame_pitch, Mq, acc, 1, cap, 30);
+                     row_pitch, frame_pitch, Mq, acc, 1, cap, kDwKw);
   return hipGetLastError();
 }
 
