@@ -273,8 +273,9 @@ struct Smem {
 };
 
 // Compound one tile (one block).  The lane's pixel rows of a full tile are loaded first,
-// so that they arrive while the window is set up.  Waves retire right after issuing
-// their flush atomics (no atomic returns a value), so no wave ever waits for them.
+// so that they arrive while the window is set up.  No flush atomic returns a value, so
+// no instruction depends on one; a wave still keeps its slot until its atomics have
+// completed (the end of a program waits for outstanding memory operations).
 // kRows: only image rows [vlo, vhi] of this frame are compounded (the cut image of the
 // tissue segmentation); tiles outside the band leave at once, tiles cut by it take the
 // per-pixel path.
