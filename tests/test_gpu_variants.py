@@ -6,7 +6,9 @@ oracle evaluates a voxel against every frame).
 Distance-weighted (usv_dw_*, tent kernel): FP32 sums against the FP64 definition --
 (sum w I, sum w) norm-wise within rel 1e-5 (the splat's bar), the volume per voxel within
 rel 1e-4 where sum w clears w_min by 1e-4; at full size, constant frames must give that
-constant wherever reached (the weights of a pixel sum to one)."""
+constant wherever reached (the weights of a pixel sum to one).
+Degenerate grids (one voxel thick along an axis, down to a single voxel) with tiny and
+ragged images through VNN, DW and the differentiable splat forward."""
 import numpy as np
 import pytest
 import torch
@@ -194,3 +196,66 @@ def test_slice_export_matches_numpy(axis, tmp_path):
         rows, cols = ref.shape[1], ref.shape[2]
         head = b"P5\n%d %d\n255\n" % (cols, rows)
         assert raw.startswith(head) and raw[len(head):] == ref[2 + c].tobytes()
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 6, 4), (5, 1, 3), (3, 9, 2), (7, 3, 1)])
+@pytest.mark.parametrize("wh", [(3, 2), (24, 20), (40, 33)])
+def test_degenerate_grids_vnn_dw_splat(dims, wh):
+    """Grids one voxel thick along an axis (down to one voxel) with tiny and ragged images:
+    VNN keys bit-exact, DW sums and splat volumes within the splat's bar (norm-wise rel
+    1e-5) of the FP64 oracle, DW volume and state where the weight clears w_min."""
+    from paper_2412_00058_amd import SplatContext
+    W, H = wh
+    say("case: degenerate grid (comparison rules, splat)", dims, "image", wh)
+    nx, ny, nz = dims
+    px = 0.25
+    g = synth.Grid(dims, (0.0, 0.0, 0.0), 1.0)
+    probe = synth.Probe(W, H, (px, px))
+    gen = synth.rng(96, nx * 100 + ny * 10 + nz, W * 100 + H)
+    F = 12
+    poses = np.empty((F, 4, 4))
+    for n in range(F):
+        ang = gen.uniform(-30.0, 30.0, size=3) * np.pi / 180.0
+        c = np.array([gen.uniform(0.0, nx), gen.uniform(0.0, ny), gen.uniform(0.0, nz)])
+        poses[n] = synth.probe_pose(c, ang, (W * px / 2.0, H * px / 2.0, 0.0))
+    frames = synth.rng(96, 1, W * 100 + H).integers(0, 256, size=(F, H, W)).astype(np.uint8)
+    fr = to_dev(frames)
+    # voxel-nearest-neighbour keys
+    vn = gpu_vnn(g, probe, 0.6)
+    vn.ingest(fr[:5], poses[:5])
+    vn.ingest(fr[5:], poses[5:])
+    ref = oracle.vnn_keys(g, frames, poses, probe, 0.6)
+    assert np.array_equal(keys_host(vn).reshape(ref.shape), ref)
+    vn.close()
+    # distance-weighted sums
+    ctx = dw_ctx(g, probe, F)
+    acc = ctx.dw_clear()
+    ctx.dw_ingest(acc, fr, to_dev(poses))
+    V, S = ctx.dw_finalize(acc, 0.05)
+    torch.cuda.synchronize()
+    Vo, Wo, So = oracle.dw_volume(g, frames, poses, probe, 0.05)
+    a = acc.cpu().numpy().astype(np.float64)
+    assert Wo.sum() > 0, "the frames reach the grid"
+    assert rel(a[1], Wo.ravel()) <= 1e-5
+    clear = np.abs(Wo - 0.05) > 1e-4
+    Sg, Vg = S.cpu().numpy(), V.cpu().numpy()
+    assert np.array_equal(Sg[clear], So[clear])
+    both = clear & (So == 1)
+    assert np.all(np.abs(Vg[both] - Vo[both]) <= 1e-4 * np.abs(Vo[both]) + 1e-4)
+    ctx.close()
+    # differentiable splat forward (FP32 intensities, per-frame se(3) perturbations)
+    I = (frames.astype(np.float32) / 255.0 - 0.3).astype(np.float32)
+    xi = np.concatenate([gen.uniform(-0.1, 0.1, size=(F, 3)), gen.uniform(-1.0, 1.0, size=(F, 3)) * np.pi / 180.0],
+                        axis=1)
+    sctx = SplatContext(g.dims, g.origin_mm, g.voxel_mm, W, H, (px, px), F)
+    vols = sctx.forward(to_dev(I), to_dev(poses), to_dev(xi))
+    torch.cuda.synchronize()
+    ref4 = oracle.splat_forward(g, I, poses, xi, probe)
+    got = vols.cpu().numpy().astype(np.float64)
+    for k in range(4):
+        r = np.asarray(ref4[k]).ravel()
+        if np.abs(r).sum() == 0:
+            assert np.abs(got[k]).sum() == 0
+        else:
+            assert rel(got[k], r) <= 1e-5, k
+    sctx.close()
