@@ -203,7 +203,8 @@ def test_slice_export_matches_numpy(axis, tmp_path):
 def test_degenerate_grids_vnn_dw_splat(dims, wh):
     """Grids one voxel thick along an axis (down to one voxel) with tiny and ragged images:
     VNN keys bit-exact, DW sums and splat volumes within the splat's bar (norm-wise rel
-    1e-5) of the FP64 oracle, DW volume and state where the weight clears w_min."""
+    1e-5) of the FP64 oracle, DW volume and state where the weight clears w_min, and the
+    splat backward's dI and per-frame pose gradients within rel 1e-3 of the oracle's."""
     from paper_2412_00058_amd import SplatContext
     W, H = wh
     say("case: degenerate grid (comparison rules, splat)", dims, "image", wh)
@@ -258,4 +259,21 @@ def test_degenerate_grids_vnn_dw_splat(dims, wh):
             assert np.abs(got[k]).sum() == 0
         else:
             assert rel(got[k], r) <= 1e-5, k
+    # backward from the oracle's volumes (as on the full workload): dI norm-wise and each
+    # frame's pose gradient within rel 1e-3 of the FP64 analytic gradient
+    ref32 = torch.from_numpy(np.stack([np.asarray(v, np.float64).ravel() for v in ref4]).astype(np.float32)).cuda()
+    _, grads = sctx.loss(ref32)
+    dI, dxi = sctx.backward(to_dev(I), to_dev(poses), to_dev(xi), grads)
+    L64, G64 = oracle.overlap_loss(ref4)
+    dI64, dxi64 = oracle.splat_backward(g, I, poses, xi, probe, G64)
+    dxi = dxi.cpu().numpy()
+    big = max(np.linalg.norm(dxi64, axis=1).max(), 1e-300)
+    for n in range(F):
+        nrm = np.linalg.norm(dxi64[n])
+        if nrm > 1e-6 * big:
+            assert np.linalg.norm(dxi[n] - dxi64[n]) <= 1e-3 * nrm, n
+        else:
+            assert np.linalg.norm(dxi[n]) <= 1e-5 * big, n
+    if np.abs(dI64).sum() > 0:
+        assert rel(dI.cpu().numpy(), dI64) <= 1e-3
     sctx.close()
