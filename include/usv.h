@@ -208,7 +208,8 @@ usv_status usv_finalize(usv_volume *vol, const usv_box *region, uint8_t *vol_u8_
 /* Bone depth + slab projection (Sec. II.D) of a finalized volume.  Outputs:
  * depth_dev int16 [nz][nx]; mean_dev and max_dev FP32 [n_half][nz][nx].  n_half 1..4,
  * half widths 0..255, k 1..64, r 0..8, y_lo >= 0, fallback_y in [0, ny) (USV_E_ARG
- * otherwise).  USV_E_STATE if pixels were added to the volume (ingest, graph launch,
+ * otherwise); grids of more than 32767 rows (ny) are USV_E_UNSUPPORTED (depths are
+ * int16).  USV_E_STATE if pixels were added to the volume (ingest, graph launch,
  * batched ingest, import) after its last usv_finalize or usv_reset: the volume's
  * outputs would not reflect them. */
 usv_status usv_segment_project(usv_volume *vol, const usv_seg_params *params, const uint8_t *vol_u8_dev,
@@ -222,8 +223,9 @@ usv_status usv_segment_project(usv_volume *vol, const usv_seg_params *params, co
  * default stream).  The raw per-column contour depths live in a fixed scratch array of
  * the library, USV_NOALLOC_MAX_COLUMNS int16 entries (4 MiB) per device, held by each
  * device the library runs on until the process ends; its device address is looked up on
- * the first call on a device.  Grids with nx * nz > USV_NOALLOC_MAX_COLUMNS return
- * USV_E_UNSUPPORTED before any device work; bad arguments return USV_E_ARG; a failed
+ * the first call on a device.  Grids with nx * nz > USV_NOALLOC_MAX_COLUMNS or more than
+ * 32767 rows return USV_E_UNSUPPORTED before any device work; bad arguments return
+ * USV_E_ARG; a failed
  * launch USV_E_DEVICE.  Every call on one device shares that scratch: calls that overlap
  * on one device (other streams, other threads) race and must be serialised by the
  * caller. */

@@ -30,6 +30,7 @@ constexpr int kMaxProbes = 16;
 // library streams that consecutive ingest launches alternate between (overlapped ingest)
 constexpr int kSides = USV_INGEST_STREAMS;
 constexpr int64_t kMaxVox = (int64_t)1 << 31;
+constexpr int32_t kMaxDepthRows = 32767;   // depth maps are int16 row indices
 constexpr double kMapLimit = 18446744073709551616.0;  // 2^64
 
 struct ProbeState {
@@ -1005,6 +1006,7 @@ usv_status usv_segment_project(usv_volume *v, const usv_seg_params *pr, const ui
     if (js != USV_OK) return js;
   }
   if (!seg_params_ok(pr, v->ny)) return fail(v, USV_E_ARG, "bad segmentation parameters");
+  if (v->ny > kMaxDepthRows) return fail(v, USV_E_UNSUPPORTED, "depth maps hold int16 rows: ny <= 32767");
   if (v->unfinalized) return fail(v, USV_E_STATE, "pixels were added since the last finalize");
   if (v->sticky == USV_E_DEVICE) return v->sticky;
   const SegArgs a = seg_args(pr, vol_u8, state, v->d_raw, depth, mean, max, v->nx, v->ny, v->nz, v->origin, v->s);
@@ -1016,7 +1018,8 @@ usv_status usv_segment_project_noalloc(const usv_grid_desc *grid, const usv_seg_
                                        void *stream) {
   if (!grid_ok(grid) || !pr || !vol_u8 || !state || !depth || !mean || !max) return USV_E_ARG;
   if (!seg_params_ok(pr, grid->dims[1])) return USV_E_ARG;
-  if ((int64_t)grid->dims[0] * grid->dims[2] > kStaticRawColumns) return USV_E_UNSUPPORTED;
+  if (grid->dims[1] > kMaxDepthRows || (int64_t)grid->dims[0] * grid->dims[2] > kStaticRawColumns)
+    return USV_E_UNSUPPORTED;
   int16_t *raw = nullptr;
   const usv_status st = static_raw_scratch(&raw);
   if (st != USV_OK) return st;

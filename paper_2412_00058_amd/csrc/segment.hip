@@ -209,6 +209,35 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
     // lower median of the valid depths: the smallest v with #{w <= v} > (n - 1) / 2,
     // found by bisection over [0, ny) (depths are column indices)
     int n = 0;
+    if (r <= 2) {
+      // the (2r + 1)^2 taps read once into registers; taps outside the window and
+      // columns without a depth hold a value above every candidate, so they never count
+      constexpr int kNone = 0x7FFF;
+      int w[25];
+#pragma unroll
+      for (int dz = 0; dz < 5; ++dz)
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) {
+          const int t = (dz <= 2 * r && dx <= 2 * r) ? (int)tile[(tz + dz) * pw + tx + dx] : -1;
+          w[dz * 5 + dx] = t >= 0 ? t : kNone;
+          n += t >= 0;
+        }
+      if (n == 0) {
+        d = a.fallback_y;
+      } else {
+        const int want = (n - 1) >> 1;
+        int lo = 0, hi = a.ny - 1;   // answer in [lo, hi]
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          int le = 0;
+#pragma unroll
+          for (int k = 0; k < 25; ++k) le += w[k] <= mid;
+          if (le > want) hi = mid;
+          else lo = mid + 1;
+        }
+        d = lo;
+      }
+    } else {
     for (int dz = 0; dz <= 2 * r; ++dz)
       for (int dx = 0; dx <= 2 * r; ++dx) n += tile[(tz + dz) * pw + tx + dx] >= 0;
     if (n == 0) {
@@ -228,6 +257,7 @@ __global__ __launch_bounds__(256) void depth_slab_kernel(SegArgs a) {
         else lo = mid + 1;
       }
       d = lo;
+    }
     }
   } else {
     double cut;

@@ -169,3 +169,13 @@ def test_binding_rejects_bad_tensors_before_any_device_call():
         extract_slices(torch.zeros((4, 4, 4), dtype=torch.uint8))
     with pytest.raises(ValueError):
         U.probe_desc(8, 6, (0.1, 0.1), None, np.ones((5, 8), np.uint8))
+
+
+def test_noalloc_projection_refuses_more_rows_than_int16_depths_hold():
+    """Depth maps are int16 row indices: a grid of 32768 rows is refused before any
+    device work (pointers are never dereferenced on this path)."""
+    L = _lib.lib()
+    p16 = C.c_void_p(16)
+    tall = U.grid_desc((4, 32768, 4))
+    assert L.usv_segment_project_noalloc(C.byref(tall), C.byref(U.seg_params(half=(2,))), p16, p16, p16, p16, p16,
+                                         None) == _lib.USV_E_UNSUPPORTED

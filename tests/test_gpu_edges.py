@@ -779,3 +779,33 @@ def test_segment_project_refuses_an_unfinalized_volume():
     vol.sync()
     assert vol.status() == 0
     vol.close()
+
+
+def test_segment_project_refuses_more_rows_than_int16_depths_hold():
+    """Depth maps are int16 row indices: a volume of 32768 rows is refused with
+    USV_E_UNSUPPORTED; 32767 rows are accepted and give the oracle's depths."""
+    from paper_2412_00058_amd import UsvError, _lib, seg_params
+    say("case: segment_project row limit")
+    prm = seg_params(r=1, k=2, fallback_y=5, half=(1,))
+    tall = synth.Grid((2, 32768, 2), (0.0, 0.0, 0.0), 0.5)
+    vol = gpu_volume(tall)
+    V, S = vol.finalize()
+    with pytest.raises(UsvError) as e:
+        vol.segment_project(prm, V, S)
+    assert e.value.status == _lib.USV_E_UNSUPPORTED
+    vol.close()
+    g = synth.Grid((2, 32767, 2), (0.0, 0.0, 0.0), 0.5)
+    vol = gpu_volume(g)
+    V, S = vol.finalize()
+    Vh = np.zeros((2, 32767, 2), np.uint8)
+    Sh = np.zeros_like(Vh)
+    Vh[:, 32760, :] = 250   # a bright voxel near the last row, over darker rows
+    Sh[:, 32760, :] = 1
+    V.copy_(torch.from_numpy(Vh))
+    S.copy_(torch.from_numpy(Sh))
+    dep, mean, mx = vol.segment_project(prm, V, S)
+    vol.sync()
+    do, mo, xo = oracle.segment(g, Vh, Sh, oracle.seg_params(mode=oracle.ALG2, r=1, k=2, fallback_y=5, half=(1,)))
+    assert np.array_equal(dep.cpu().numpy(), do) and int(do.max()) == 32760
+    assert np.array_equal(mean.cpu().numpy().view(np.uint32), mo.view(np.uint32))
+    vol.close()
