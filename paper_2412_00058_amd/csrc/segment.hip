@@ -49,11 +49,16 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
   const int z = gl < total ? (int)(gl / groups) : 0;
   const int x = gl < total ? (int)(gl - (uint32_t)z * groups) * kC : a.nx;   // first column of this lane
   const int ymax = a.ny - 1 - a.k;
+  // a score is k h - (sum of the k rows below), within +-64 * 255; the threshold k tau_G
+  // clamped to +-2^20 decides every comparison as the exact product would.  Starting the
+  // running best at thr - 1 makes "score > best" also mean "score >= thr", and lets the
+  // first qualifying row in without a separate test
+  const int thr = (int)max((long long)-(1 << 20), min((long long)(1 << 20), (long long)a.k * a.tau_G));
   int best[kC], best_s[kC];
 #pragma unroll
   for (int c = 0; c < kC; ++c) {
     best[c] = -1;
-    best_s[c] = 0;
+    best_s[c] = thr - 1;
   }
   // row offsets are 32-bit (a plane holds < 2^32 bytes) and wave-uniform: each load is
   // one 64-bit add of a scalar offset to the lane's column pointer
@@ -79,13 +84,12 @@ __global__ __launch_bounds__(256) void raw_depth_kernel(SegArgs a) {
 #pragma unroll
         for (int c = 0; c < kC; ++c) below[c] += (int)((w >> (8 * c)) & 0xFFu);
       }
-      const int thr = a.k * a.tau_G;
       auto score_row = [&](int y, uint32_t hv, uint32_t lv) {
 #pragma unroll
         for (int c = 0; c < kC; ++c) {
           const int h = (int)((hv >> (8 * c)) & 0xFFu), l = (int)((lv >> (8 * c)) & 0xFFu);
           const int sc = (int)__umul24((uint32_t)a.k, (uint32_t)h) - below[c];   // k <= 64, h <= 255
-          if (h >= a.tau_I && sc >= thr && (best[c] < 0 || sc > best_s[c])) {
+          if (h >= a.tau_I && sc > best_s[c]) {
             best[c] = y;
             best_s[c] = sc;
           }
