@@ -4,7 +4,8 @@
 //   Alg. 1 (Table I Step 4): host, FP64, from the pose -- per frame one depth of cut;
 //   Alg. 2 (Table II Steps 2-3): the contour scan of the volume path run over the frame
 //     stack (raw contour row per image column), then
-//       image_median_kernel: per frame the lower median of its valid contour rows;
+//       image_median_hist_kernel (images of at most 4096 rows) or image_median_kernel:
+//                            per frame the lower median of its valid contour rows;
 //       cut_band_kernel    : per frame the lower median of those over the frames
 //                            [f - r, f + r] (median filter across images) and the band.
 #include <cmath>
@@ -56,6 +57,52 @@ __global__ __launch_bounds__(256) void image_median_kernel(const int16_t *__rest
   if (threadIdx.x == 0) cn[f] = (int16_t)lo;
 }
 
+// The same lower median from a histogram of the frame's contour rows in LDS, for images
+// of at most kHistRows rows: one pass of LDS atomics, then one block-wide prefix sum over
+// the bins; the thread whose bins hold rank floor((m-1)/2) walks them to the row.
+constexpr int kHistRows = 4096;
+__global__ __launch_bounds__(256) void image_median_hist_kernel(const int16_t *__restrict__ raw, int W, int H,
+                                                                int16_t *__restrict__ cn) {
+  __shared__ int hist[kHistRows];
+  __shared__ int wsum[4];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int16_t *r = raw + (int64_t)f * W;
+  for (int b = tid; b < H; b += 256) hist[b] = 0;
+  __syncthreads();
+  for (int u = tid; u < W; u += 256) {
+    const int y = r[u];
+    if (y >= 0) atomicAdd(&hist[y], 1);   // contour rows lie in [0, H)
+  }
+  __syncthreads();
+  // thread t owns bins [t per, min((t + 1) per, H))
+  const int per = (H + 255) / 256, b0 = min(tid * per, H), b1 = min(b0 + per, H);
+  int mine = 0;
+  for (int b = b0; b < b1; ++b) mine += hist[b];
+  // inclusive prefix of the per-thread counts: within the wave, then across the 4 waves
+  const int lane = tid & 63, wv = tid >> 6;
+  int inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int before = inc - mine;
+  for (int k = 0; k < wv; ++k) before += wsum[k];
+  const int m = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  if (m == 0) {
+    if (tid == 0) cn[f] = -1;
+    return;
+  }
+  const int k = (m - 1) / 2;
+  if (before <= k && k < before + mine) {
+    int acc = before, b = b0;
+    while (acc + hist[b] <= k) acc += hist[b++];
+    cn[f] = (int16_t)b;
+  }
+}
+
 // One thread per frame: lower median of the valid per-image depths over [f - r, f + r]
 // (clipped to the sweep), by rank counting (window of at most 129 frames) over the
 // block's frames and their r-halo staged in LDS.
@@ -102,7 +149,10 @@ __global__ __launch_bounds__(kBandBlock) void cut_band_kernel(const int16_t *__r
 hipError_t launch_image_cut(const int16_t *raw, int F, int W, int H, int r, int fallback, int h, int16_t *cn,
                             int32_t *rows, hipStream_t s) {
   if (F <= 0) return hipSuccess;
-  hipLaunchKernelGGL(image_median_kernel, dim3(F), dim3(256), 0, s, raw, W, H, cn);
+  if (H <= kHistRows)
+    hipLaunchKernelGGL(image_median_hist_kernel, dim3(F), dim3(256), 0, s, raw, W, H, cn);
+  else
+    hipLaunchKernelGGL(image_median_kernel, dim3(F), dim3(256), 0, s, raw, W, H, cn);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cut_band_kernel, dim3((F + kBandBlock - 1) / kBandBlock), dim3(kBandBlock), 0, s, cn, F, r,
