@@ -31,6 +31,26 @@ def test_alg2_bands_small_sweep():
     assert (ref[:, 0] > 0).all()
 
 
+@pytest.mark.parametrize("H", [4096, 4200])
+def test_alg2_bands_per_frame_median_both_forms(H):
+    """Images of up to 4096 rows take the histogram median, taller ones the bisection:
+    contours spread over the whole height (and a frame without any) give the oracle's bands
+    with either."""
+    say("case: alg2 bands, H", H)
+    g = synth.rng(12, H, 0)
+    F, W = 9, 48
+    fr = g.integers(0, 60, size=(F, H, W)).astype(np.uint8)
+    for f in range(F):
+        ys = g.integers(10, H - 10, size=W)   # one contour row per column, anywhere
+        for x in range(W):
+            fr[f, ys[x], x] = 240
+            fr[f, ys[x] + 1:, x] //= 8
+    fr[4] = 30                                  # no contour in this frame
+    kw = dict(y_lo=3, k=4, tau_I=150, tau_G=30, r=2, fallback_row=H // 2, half_rows=20)
+    ref = oracle.cut_rows_alg2(fr, **kw)
+    assert np.array_equal(alg2_gpu(to_dev(fr), **kw), ref)
+
+
 @pytest.mark.parametrize("W", [37, 64])
 def test_alg2_bands_odd_width_and_pitched_stack(W):
     """W = 37 takes the one-column-per-lane scan; the W = 64 frames are a column slice of
