@@ -328,7 +328,8 @@ usv_status usv_ingest_batched(usv_volume *const *vols, const int32_t *probe_ids,
 
 /* Autotune the ingest tiling of a probe on sample data (n >= 1 frames) by timing
  * every candidate tile shape on a scratch copy of the grid, then 16 and 32 frames per
- * launch for the best shape; the winners become the probe's tiling and launch size.
+ * launch for the best shape (kept only if at least 3 % faster than 64); the winners
+ * become the probe's tiling and launch size.
  * A trial submits the sample as ingest calls of 64 frames (host pose folding included)
  * and launches the way the volume currently does (serial, or overlapped after
  * usv_set_ingest_overlap), so set the mode first.  cache_path (nullable): results are

@@ -1386,9 +1386,14 @@ usv_status usv_autotune(usv_volume *v, int32_t probe_id, const uint8_t *frames, 
       best = t;
     }
   }
+  // A smaller launch is kept only if at least 3 % faster: the sample is a short burst, and
+  // its last launch's tail (shorter for smaller launches) weighs more in it than in a sweep
+  // (whole-spine sweep: 64 frames per launch 0.955 ms per step, 32 frames 0.99 ms, though
+  // the 1024-frame trial had timed 32 faster).
+  const float chunk_ms = best_ms * 0.97f;
   for (int ch : {16, 32}) {
     const float ms = trial(best, ch);
-    if (ms >= 0.0f && ms < best_ms) {
+    if (ms >= 0.0f && ms < chunk_ms && ms < best_ms) {
       best_ms = ms;
       best_chunk = ch;
     }
