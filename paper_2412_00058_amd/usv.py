@@ -336,7 +336,9 @@ class Volume:
         self._joined()
 
     def autotune(self, probe_id, frames: torch.Tensor, poses, cache_path: Optional[str] = None):
+        _check_frames(frames, self._probe_hw.get(probe_id))
         P = _poses(poses)
+        _need(P.shape[0] == frames.shape[0] >= 1, "autotune: at least one frame, one pose per frame")
         check(lib().usv_autotune(self.h, probe_id, _vp(frames), frames.stride(1), frames.stride(0),
                                  P.ctypes.data_as(C.c_void_p), frames.shape[0],
                                  cache_path.encode() if cache_path else None), self.h)
@@ -357,12 +359,15 @@ def ingest_batched(jobs: Sequence[tuple]):
     any pending overlapped burst of the volumes is joined.  Returns the dirty boxes."""
     n = len(jobs)
     L = lib()
+    P = [_poses(j[3]) for j in jobs]
+    for j, p in zip(jobs, P):
+        _check_frames(j[2], j[0]._probe_hw.get(int(j[1])))
+        _need(p.shape[0] == j[2].shape[0], "one pose per frame")
     vols = (C.c_void_p * n)(*[j[0].h for j in jobs])
     pids = (C.c_int32 * n)(*[int(j[1]) for j in jobs])
     frames = (C.c_void_p * n)(*[j[2].data_ptr() for j in jobs])
     rp = (C.c_int64 * n)(*[j[2].stride(1) for j in jobs])
     fp = (C.c_int64 * n)(*[j[2].stride(0) for j in jobs])
-    P = [_poses(j[3]) for j in jobs]
     pp = (C.c_void_p * n)(*[p.ctypes.data for p in P])
     nf = (C.c_int32 * n)(*[int(j[2].shape[0]) for j in jobs])
     boxes = (Box * n)()
@@ -370,6 +375,17 @@ def ingest_batched(jobs: Sequence[tuple]):
     for j in jobs:
         j[0]._joined()
     return list(boxes)
+
+
+def _host_frame(frame_host, pose, hw):
+    """One host frame (H*W bytes, row pitch W) and its 16-double pose, checked against the
+    probe's image size: the library copies exactly H*W bytes from the frame's address."""
+    f = np.ascontiguousarray(frame_host, dtype=np.uint8)
+    _need(hw is None or f.size == hw[0] * hw[1],
+          "host frame: %d bytes, the probe's image holds %s" % (f.size, "x".join(map(str, hw or ()))))
+    P = np.ascontiguousarray(pose, dtype=np.float64)
+    _need(P.size == 16, "pose: 16 values (4x4 row major)")
+    return f, P.reshape(16)
 
 
 class Graph:
@@ -381,10 +397,10 @@ class Graph:
         vol._joined()
         self.h = h
         self.vol = vol
+        self.hw = vol._probe_hw.get(probe_id)
 
     def launch(self, frame_host: np.ndarray, pose) -> Box:
-        f = np.ascontiguousarray(frame_host, dtype=np.uint8)
-        P = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+        f, P = _host_frame(frame_host, pose, self.hw)
         box = Box()
         check(lib().usv_graph_launch(self.h, f.ctypes.data_as(C.c_void_p), P.ctypes.data_as(C.c_void_p),
                                      C.byref(box)), self.vol.h)
@@ -422,10 +438,10 @@ class Pipeline:
                                         _vp(self.depth), _vp(self.mean), _vp(self.max), C.byref(h)), vol.h)
         self.h = h
         self.vol = vol
+        self.hw = vol._probe_hw.get(probe_id)
 
     def push(self, frame_host: np.ndarray, pose):
-        f = np.ascontiguousarray(frame_host, dtype=np.uint8)
-        P = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+        f, P = _host_frame(frame_host, pose, self.hw)
         check(lib().usv_pipeline_push(self.h, f.ctypes.data_as(C.c_void_p), P.ctypes.data_as(C.c_void_p)),
               self.vol.h)
 
@@ -495,12 +511,13 @@ class VNN:
                                    C.byref(h)))
         del keep
         self.h = h
+        self.hw = (int(height), int(width))
 
     def reset(self):
         check(lib().usv_vnn_reset(self.h))
 
     def ingest(self, frames: torch.Tensor, poses):
-        _check_frames(frames)
+        _check_frames(frames, self.hw)
         P = _poses(poses)
         _need(P.shape[0] == frames.shape[0], "one pose per frame")
         check(lib().usv_vnn_ingest(self.h, _vp(frames), frames.stride(1), frames.stride(0),

@@ -676,9 +676,9 @@ def test_finalize_extreme_counts_and_sums():
 
 
 def test_binding_checks_tensor_sizes():
-    """Frames smaller than the probe image, outputs shorter than the grid and host tensors
-    are refused by the binding with ValueError (no device work is issued for them); the
-    volume is still usable afterwards."""
+    """Frames smaller than the probe image (device tensors, and host frames for a captured
+    graph), outputs shorter than the grid and host tensors are refused by the binding with
+    ValueError (no device work is issued for them); the volume is still usable afterwards."""
     say("case: binding size checks")
     d = synth.cfg1()
     g = d["grid"]
@@ -697,6 +697,20 @@ def test_binding_checks_tensor_sizes():
         vol.finalize(out=(V, None))
     with pytest.raises(ValueError):
         vol.export_accumulators(torch.empty(4, dtype=torch.int32, device="cuda"))
+    from paper_2412_00058_amd import Graph
+    gr = Graph(vol, pid)
+    with pytest.raises(ValueError):
+        gr.launch(d["frames"][0][:-1], d["poses"][0])              # host frame one row short
+    with pytest.raises(ValueError):
+        gr.launch(d["frames"][0], d["poses"][0][:3])               # pose of 12 values
+    gr.close()
+    from paper_2412_00058_amd import ingest_batched
+    with pytest.raises(ValueError):
+        ingest_batched([(vol, pid, fr[:4, :-1], d["poses"][:4])])   # one row short
+    with pytest.raises(ValueError):
+        ingest_batched([(vol, pid, fr[:4], d["poses"][:3])])        # one pose missing
+    with pytest.raises(ValueError):
+        vol.autotune(pid, fr[:4, :-1], d["poses"][:4])              # one row short
     vol.ingest(pid, fr[:8], d["poses"][:8])
     vol.sync()
     acc = oracle.Accum(g)

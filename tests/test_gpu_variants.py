@@ -46,6 +46,8 @@ def test_vnn_small_sweep_all_voxels():
     assert np.array_equal(V.cpu().numpy(), Vo) and np.array_equal(S.cpu().numpy(), So)
     assert So.sum() > 0.2 * So.size
     vn.reset()
+    with pytest.raises(ValueError):
+        vn.ingest(fr[:5, :, :-1], d["poses"][:5])   # frames one column narrower than the probe image
     vn.ingest(fr[:5], d["poses"][:5])
     ref5 = oracle.vnn_keys(d["grid"], d["frames"][:5], d["poses"][:5], d["probe"], 0.5)
     assert np.array_equal(keys_host(vn).reshape(ref.shape), ref5)
