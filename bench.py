@@ -486,7 +486,8 @@ def bench_batched(torch, usv, plan, frames4, steps):
     with its own grid) with their own distinct frames, compounded by one batched launch
     per pass.  Each probe type is autotuned first on 256 of its frames.  Returns (frames/s,
     ms per pass, frames, in-mask pixel bytes per pass, frames/s of the same sweeps through
-    plain calls of 64 frames with overlapped launches)."""
+    plain calls of 64 frames with overlapped launches, pixels kept by one pass: the sum of
+    the uint16 counts the accumulators hold after it)."""
     jobs = []
     total = 0
     px_bytes = 0
@@ -514,6 +515,9 @@ def bench_batched(torch, usv, plan, frames4, steps):
         usv.ingest_batched(jobs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    kept = 0
+    for vol, _, _, _ in jobs:   # the accumulators hold exactly the last pass
+        kept += int((vol.cnt.to(torch.int32) & 0xFFFF).sum(dtype=torch.int64).item())
     # the same sweeps through plain calls of 64 frames (overlapped launches), for comparison
     for j in jobs:
         j[0].set_ingest_overlap(True)
@@ -537,7 +541,7 @@ def bench_batched(torch, usv, plan, frames4, steps):
             raise RuntimeError("batched ingest reported an error")
     for j in jobs:
         j[0].close()
-    return total / dt, dt * 1e3, total, px_bytes, total / dtp
+    return total / dt, dt * 1e3, total, px_bytes, total / dtp, kept
 
 
 def bench_pinned(torch, usv, d, reps=2):
@@ -951,13 +955,21 @@ def main():
         except Exception as e:
             extras["realtime_error"] = repr(e)
         try:
-            fps, ms, tot, pxb, fps_plain = bench_batched(torch, usv, plan4, frames4, max(2, min(args.steps, 5)))
+            fps, ms, tot, pxb, fps_plain, kept = bench_batched(torch, usv, plan4, frames4, max(2, min(args.steps, 5)))
             extras["batched_frames_per_s"] = round(fps, 1)
             extras["batched_same_frames_plain_calls_frames_per_s"] = round(fps_plain, 1)
             extras["batched_ms_per_pass"] = round(ms, 3)
             extras["batched_frames"] = tot
             extras["batched_pixel_GBps"] = round(pxb / (ms * 1e-3) / 1e9, 1)
             extras["batched_hbm_frac_pixels_only"] = round(pxb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            # the batched kernel's ALU floor, as for the plain launch: ALU_OPS_PER_PIXEL lane
+            # operations per kept pixel; the pass time also holds the 16 volumes' resets
+            floor_ms = ALU_OPS_PER_PIXEL * kept / ALU_PEAK_OPS * 1e3
+            extras["batched_roofline"] = {
+                "bound": "alu", "kept_pixels": kept, "alg_ops_per_pass": ALU_OPS_PER_PIXEL * kept,
+                "achieved": round(ALU_OPS_PER_PIXEL * kept / (ms * 1e-3) / 1e12, 2), "peak": ALU_PEAK_OPS / 1e12,
+                "unit": "TOP/s", "floor_ms": round(floor_ms, 3), "frac": round(floor_ms / ms, 4),
+                "pass_ms": round(ms, 3)}
         except Exception as e:
             extras["batched_error"] = repr(e)
         try:
