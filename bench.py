@@ -1028,6 +1028,21 @@ def main():
            "event_ms_per_step": {"median": round(float(np.median(ev_ms)), 4), "min": round(float(np.min(ev_ms)), 4),
                                  "runs": len(ev_ms), "warmup": 2},
            "roofline": roof, "cpu_baseline": cpu}
+    if not args.profile_pass:
+        # finalize phase (zero fill of the outputs + stencil) against its HBM floor: the
+        # accumulators of the live box (touched box dilated by one) read once, 6 B per voxel,
+        # and V + state written for the whole grid, 2 B per voxel
+        tb = usv.dirty_box(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, p.calib, d["poses"])
+        live = 1
+        for k in range(3):
+            live *= max(0, min(g.dims[k], tb.hi[k] + 1) - max(0, tb.lo[k] - 1))
+        nvox = g.dims[0] * g.dims[1] * g.dims[2]
+        fbytes = 6 * live + 2 * nvox
+        ffloor = fbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+        out["finalize_roofline"] = {"bound": "hbm", "alg_bytes": int(fbytes), "live_voxels": int(live),
+                                    "floor_ms": round(ffloor, 4), "phase_ms": round(phase[1], 4),
+                                    "achieved": round(fbytes / (phase[1] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                    "unit": "GB/s", "frac": round(ffloor / phase[1], 4) if phase[1] > 0 else None}
     out.update(extras)
     print(json.dumps(out))
 
