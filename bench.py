@@ -1029,20 +1029,35 @@ def main():
                                  "runs": len(ev_ms), "warmup": 2},
            "roofline": roof, "cpu_baseline": cpu}
     if not args.profile_pass:
-        # finalize phase (zero fill of the outputs + stencil) against its HBM floor: the
-        # accumulators of the live box (touched box dilated by one) read once, 6 B per voxel,
-        # and V + state written for the whole grid, 2 B per voxel
-        tb = usv.dirty_box(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, p.calib, d["poses"])
-        live = 1
-        for k in range(3):
-            live *= max(0, min(g.dims[k], tb.hi[k] + 1) - max(0, tb.lo[k] - 1))
-        nvox = g.dims[0] * g.dims[1] * g.dims[2]
-        fbytes = 6 * live + 2 * nvox
-        ffloor = fbytes / (HBM_PEAK_GBS * 1e9) * 1e3
-        out["finalize_roofline"] = {"bound": "hbm", "alg_bytes": int(fbytes), "live_voxels": int(live),
-                                    "floor_ms": round(ffloor, 4), "phase_ms": round(phase[1], 4),
-                                    "achieved": round(fbytes / (phase[1] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                                    "unit": "GB/s", "frac": round(ffloor / phase[1], 4) if phase[1] > 0 else None}
+        try:
+            # finalize phase (zero fill of the outputs + stencil) against its HBM floor: the
+            # accumulators of the live box (touched box dilated by one) read once, 6 B per voxel,
+            # and V + state written for the whole grid, 2 B per voxel
+            tb = usv.dirty_box(g.dims, g.origin_mm, g.voxel_mm, p.width, p.height, p.pixel_mm, p.calib, d["poses"])
+            live = 1
+            for k in range(3):
+                live *= max(0, min(g.dims[k], tb.hi[k] + 1) - max(0, tb.lo[k] - 1))
+            nvox = g.dims[0] * g.dims[1] * g.dims[2]
+            fbytes = 6 * live + 2 * nvox
+            ffloor = fbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+            out["finalize_roofline"] = {"bound": "hbm", "alg_bytes": int(fbytes), "live_voxels": int(live),
+                                        "floor_ms": round(ffloor, 4), "phase_ms": round(phase[1], 4),
+                                        "achieved": round(fbytes / (phase[1] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": round(ffloor / phase[1], 4) if phase[1] > 0 else None}
+            # depth map + slab projection against its HBM floor: V read once over the scanned
+            # rows [y_lo, ny), state over each column's widest slab, the depth map and the mean /
+            # max projections written
+            nx, ny, nz = g.dims
+            hmax = max(SEG["half"])
+            sbytes = (nx * nz * (ny - SEG["y_lo"]) + nx * nz * min(ny, 2 * hmax + 1)
+                      + 2 * nx * nz + 2 * 4 * len(SEG["half"]) * nx * nz)
+            sfloor = sbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+            out["segment_roofline"] = {"bound": "hbm", "alg_bytes": int(sbytes), "floor_ms": round(sfloor, 4),
+                                       "phase_ms": round(phase[2], 4),
+                                       "achieved": round(sbytes / (phase[2] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(sfloor / phase[2], 4) if phase[2] > 0 else None}
+        except Exception as e:   # the main line is printed whatever happens here
+            out["phase_roofline_error"] = repr(e)
     out.update(extras)
     print(json.dumps(out))
 
