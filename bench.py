@@ -914,6 +914,15 @@ def main():
             fps, ms = bench_splat(torch, usv, max(3, min(args.steps, 10)), d5)
             extras["fwd_bwd_frames_per_s"] = round(fps, 1)
             extras["fwd_bwd_ms_per_step"] = round(ms, 3)
+            # forward + loss + backward against the HBM floor: per pixel I read twice and dI
+            # written (4 B each), per voxel the four FP32 volumes written, read by the loss,
+            # its four gradients written and read by the backward (16 B each)
+            npx, nv5 = int(np.prod(d5["I"].shape)), int(d5["grid"].nvox)
+            b5 = 12 * npx + 64 * nv5
+            f5 = b5 / (HBM_PEAK_GBS * 1e9) * 1e3
+            extras["fwd_bwd_roofline"] = {"bound": "hbm", "alg_bytes": b5, "floor_ms": round(f5, 4),
+                                          "step_ms": round(ms, 3), "achieved": round(b5 / (ms * 1e-3) / 1e9, 1),
+                                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(f5 / ms, 4)}
         except Exception as e:  # report, do not hide
             extras["fwd_bwd_error"] = repr(e)
         try:
